@@ -59,6 +59,10 @@ def _load():
             ctypes.c_uint, ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p,
             ctypes.c_size_t, ctypes.c_int]
         lib.ppc_oracle_pospopcnt_mt.restype = ctypes.c_int
+        lib.ppc_oracle_sweep.argtypes = [
+            ctypes.c_uint, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_size_t,
+            ctypes.POINTER(ctypes.c_uint64)]
+        lib.ppc_oracle_sweep.restype = ctypes.c_int
         lib.ppc_oracle_popcount.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
         lib.ppc_oracle_popcount.restype = ctypes.c_uint64
         _lib = lib
@@ -102,6 +106,20 @@ def pospopcnt_mt(data, w: int, nthreads: int) -> np.ndarray:
     rc = _load().ppc_oracle_pospopcnt_mt(
         w, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
         buf.ctypes.data if buf.size else None, buf.size, int(nthreads))
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    return out
+
+
+def sweep(data, w: int, max_len: int, n_offsets: int) -> np.ndarray:
+    """pospopcnt of every window data[o:o+n], o < n_offsets, n <= max_len.
+    Returns an array of shape (n_offsets, max_len + 1, w)."""
+    buf = _as_u8(data)
+    if buf.size < n_offsets - 1 + max_len:
+        raise ValueError("buffer too short for the sweep")
+    out = np.zeros((n_offsets, max_len + 1, w), dtype=np.uint64)
+    rc = _load().ppc_oracle_sweep(w, buf.ctypes.data, max_len, n_offsets,
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     return out

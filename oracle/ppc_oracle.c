@@ -126,6 +126,22 @@ int ppc_oracle_pospopcnt_mt(unsigned w, uint64_t *counts, const void *buf,
     return ORACLE_OK;
 }
 
+/* Every (offset, length) window of one buffer, for the short/unaligned
+ * sweep: out[((o * (max_len + 1)) + n) * w + j] = pospopcnt_w of
+ * buf[o .. o+n) at position j, for o < n_offsets and n <= max_len.  Each
+ * window is one independent evaluation of the definition above. */
+int ppc_oracle_sweep(unsigned w, const void *buf, size_t max_len, size_t n_offsets,
+                     uint64_t *out)
+{
+    if (!width_ok(w) || buf == NULL || out == NULL)
+        return ORACLE_EINVAL;
+    const unsigned char *p = (const unsigned char *)buf;
+    for (size_t o = 0; o < n_offsets; o++)
+        for (size_t n = 0; n <= max_len; n++)
+            pospop_words(w, out + ((o * (max_len + 1)) + n) * w, p + o, n);
+    return ORACLE_OK;
+}
+
 /* Conventional population count of a byte range (the quantity the
  * Harley-Seal algorithm of Section 3.3 computes), one bit at a time. */
 uint64_t ppc_oracle_popcount(const void *buf, size_t nbytes)

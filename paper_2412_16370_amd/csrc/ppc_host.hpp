@@ -1,0 +1,20 @@
+// ppc_host.hpp -- host-side helpers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ppc.h"
+
+namespace ppc {
+
+// Number of compute units of a device (cached; 256 on MI355X).
+int device_cus(int device);
+
+// Plain call on an explicit stream (argument checks included).
+ppc_status plain_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, hipStream_t st);
+
+// Wave cap of the plain call's grid on a device.
+unsigned plain_wave_cap(int device);
+
+}  // namespace ppc

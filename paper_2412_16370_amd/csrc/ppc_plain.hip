@@ -1,0 +1,310 @@
+// ppc_plain.hip -- the plain single-array pospopcnt call and the read
+// roofline kernel for gfx950.
+//
+// Algorithm (Section 4 of the paper, re-laid out for a GPU):
+//   head/tail  : bytes before the first and after the last 16-byte aligned
+//                chunk are loaded one per lane by wave 0 and entered as
+//                single-byte chunks (head processing, Section 4.1; tail,
+//                Section 4.5).  Nothing outside [buf, buf+nbytes) is read.
+//   main loop  : each wave walks tiles of 64 lanes x 16 chunks (16 KiB); per
+//                tile every lane runs the CSA_{16+4} network (Section 4.2)
+//                and adds the weight-16 plane to a bit-sliced counter
+//                (the role of the intermediate accumulation, Section 4.3).
+//   overflow   : a segment holds at most 2^K1 - 1 tiles so the bit-sliced
+//                counter cannot overflow (Section 4.3's flush rule, with the
+//                bound proven at compile time instead of tracked at run time).
+//   final acc. : planes -> 64 integer counts per wave by cross-lane
+//                transposes and popcounts (Section 4.4).
+//   f_w        : per-block LDS partials are folded to w positions relative
+//                to `buf` and added to `counts` with 64-bit atomics.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <atomic>
+
+#include "ppc.h"
+#include "ppc_device.hpp"
+#include "ppc_host.hpp"
+
+namespace ppc {
+
+struct PlainArgs {
+    const uint4 *body;          // first full 16-byte chunk
+    uint64_t n_chunks;          // full chunks in the body
+    uint32_t n_full_tiles;      // tiles whose 1024 chunks are all in the body
+    uint32_t n_tiles;           // n_full_tiles, + 1 if a partial tile remains
+    const uint8_t *edge0;       // head bytes (lanes 0..31 of wave 0)
+    const uint8_t *edge1;       // tail bytes (lanes 32..63 of wave 0)
+    uint32_t edge0_len, edge1_len;
+    unsigned long long *counts; // w uint64 counters
+    uint32_t width;             // 8, 16, 32, 64
+    uint32_t m;                 // buf mod (w/8)
+};
+
+__device__ __forceinline__ void load_tile(uint4 (&v)[kLoadsPerTile], const uint4 *p) {
+#pragma unroll
+    for (int j = 0; j < kLoadsPerTile; ++j) v[j] = p[j * kWave];
+}
+
+template <int K1, int WPB>
+__global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
+    constexpr uint32_t kSeg = (1u << K1) - 1u;
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t wib = threadIdx.x / kWave;
+    const uint32_t gw = blockIdx.x * WPB + wib;
+    const uint32_t nw = gridDim.x * WPB;
+
+    Planes<K1> pl;
+    pl.clear();
+    uint32_t acc = 0;
+    bool any = false;
+
+    if (gw == 0) {  // head and tail bytes, one per lane
+        uint4 e = zero4();
+        if (lane < 32) {
+            if (lane < a.edge0_len) e = byte_as_chunk((uint64_t)(a.edge0 + lane), a.edge0[lane]);
+        } else if (lane - 32 < a.edge1_len) {
+            e = byte_as_chunk((uint64_t)(a.edge1 + (lane - 32)), a.edge1[lane - 32]);
+        }
+        pl.a1 = e;
+        any = true;
+    }
+
+    uint32_t seg = 0;
+    uint32_t t = gw;
+    for (; t < a.n_full_tiles; t += nw) {
+        uint4 v[kLoadsPerTile];
+        load_tile(v, a.body + (uint64_t)t * kTileChunks + lane);
+        pl.add16(pl.csa16(v));
+        any = true;
+        if (++seg == kSeg) {
+            acc += planes_position_counts<K1>(pl);
+            pl.clear();
+            seg = 0;
+        }
+    }
+    if (t < a.n_tiles) {  // the one partial tile, loads predicated
+        uint4 v[kLoadsPerTile];
+        const uint64_t base = (uint64_t)t * kTileChunks + lane;
+#pragma unroll
+        for (int j = 0; j < kLoadsPerTile; ++j) {
+            const uint64_t idx = base + (uint64_t)j * kWave;
+            v[j] = idx < a.n_chunks ? a.body[idx] : zero4();
+        }
+        pl.add16(pl.csa16(v));
+        any = true;
+    }
+    if (any) acc += planes_position_counts<K1>(pl);
+
+    __shared__ uint32_t part[WPB][kWave];
+    part[wib][lane] = acc;
+    __syncthreads();
+    if (threadIdx.x < a.width) {
+        const uint32_t s = a.width >> 3;
+        const uint32_t j = threadIdx.x;
+        const uint32_t k = j & 7u;
+        const uint32_t a0 = ((j >> 3) + a.m) & (s - 1u);
+        unsigned long long sum = 0;
+        for (uint32_t slot = a0; slot < 8u; slot += s)
+#pragma unroll
+            for (int wv = 0; wv < WPB; ++wv) sum += part[wv][8u * slot + k];
+        if (sum) atomicAdd(a.counts + j, sum);
+    }
+}
+
+// Read roofline: same tiles, same loads; sums the 64-bit words.
+template <int WPB>
+__global__ __launch_bounds__(WPB *kWave) void read_roofline_kernel(const uint4 *body, uint32_t n_tiles,
+                                                                   unsigned long long *sink) {
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t gw = blockIdx.x * WPB + threadIdx.x / kWave;
+    const uint32_t nw = gridDim.x * WPB;
+    uint64_t s0 = 0, s1 = 0;
+    for (uint32_t t = gw; t < n_tiles; t += nw) {
+        uint4 v[kLoadsPerTile];
+        load_tile(v, body + (uint64_t)t * kTileChunks + lane);
+#pragma unroll
+        for (int j = 0; j < kLoadsPerTile; ++j) {
+            s0 += ((uint64_t)v[j].y << 32) | v[j].x;
+            s1 += ((uint64_t)v[j].w << 32) | v[j].z;
+        }
+    }
+    uint64_t s = s0 + s1;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+    if (lane == 0 && s) atomicAdd(sink, (unsigned long long)s);
+}
+
+// ---- host side -----------------------------------------------------------
+static std::atomic<unsigned> g_plain_waves{0};        // 0 = default
+static std::atomic<unsigned> g_plain_wpb{4};
+
+template <int K1>
+static hipError_t launch_plain_k(const PlainArgs &a, unsigned blocks, unsigned wpb, hipStream_t st) {
+    switch (wpb) {
+    case 1: hipLaunchKernelGGL((pospop_plain_kernel<K1, 1>), dim3(blocks), dim3(64), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((pospop_plain_kernel<K1, 2>), dim3(blocks), dim3(128), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((pospop_plain_kernel<K1, 4>), dim3(blocks), dim3(256), 0, st, a); break;
+    default: hipLaunchKernelGGL((pospop_plain_kernel<K1, 8>), dim3(blocks), dim3(512), 0, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_plain(const PlainArgs &a, int k1, unsigned blocks, unsigned wpb, hipStream_t st) {
+    switch (k1) {
+    case 1: return launch_plain_k<1>(a, blocks, wpb, st);
+    case 2: return launch_plain_k<2>(a, blocks, wpb, st);
+    case 3: return launch_plain_k<3>(a, blocks, wpb, st);
+    case 4: return launch_plain_k<4>(a, blocks, wpb, st);
+    default: return launch_plain_k<5>(a, blocks, wpb, st);
+    }
+}
+
+// Smallest K1 whose segment (2^K1 - 1 tiles) covers a wave's share.
+static int pick_k1(uint64_t tiles_per_wave) {
+    int k1 = 1;
+    while (k1 < 5 && ((1ull << k1) - 1ull) < tiles_per_wave) ++k1;
+    return k1;
+}
+
+unsigned plain_wave_cap(int device) {
+    unsigned w = g_plain_waves.load(std::memory_order_relaxed);
+    if (w) return w;
+    return (unsigned)device_cus(device) * 8u;  // two waves per SIMD
+}
+
+// One launch over a range the caller has sized with kMaxTilesPerWave.
+static ppc_status plain_launch_range(unsigned width, uint64_t *counts, const uint8_t *buf, size_t nbytes,
+                                     uint32_t m, hipStream_t st) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
+    const uintptr_t b0 = (uintptr_t)buf;
+    const uintptr_t b1 = b0 + nbytes;
+    const uintptr_t f = (b0 + 15u) & ~(uintptr_t)15u;  // first full chunk
+    const uintptr_t e = b1 & ~(uintptr_t)15u;           // end of full chunks
+    PlainArgs a{};
+    a.counts = reinterpret_cast<unsigned long long *>(counts);
+    a.width = width;
+    a.m = m;
+    if (f < e) {
+        a.body = reinterpret_cast<const uint4 *>(f);
+        a.n_chunks = (uint64_t)(e - f) / 16u;
+        a.edge0 = buf;
+        a.edge0_len = (uint32_t)(f - b0);
+        a.edge1 = reinterpret_cast<const uint8_t *>(e);
+        a.edge1_len = (uint32_t)(b1 - e);
+    } else {  // fewer than two chunk boundaries: every byte is an edge byte
+        a.body = nullptr;
+        a.n_chunks = 0;
+        a.edge0 = buf;
+        a.edge0_len = (uint32_t)nbytes;  // <= 30
+        a.edge1 = nullptr;
+        a.edge1_len = 0;
+    }
+    a.n_full_tiles = (uint32_t)(a.n_chunks / kTileChunks);
+    a.n_tiles = (uint32_t)((a.n_chunks + kTileChunks - 1) / kTileChunks);
+    const unsigned wpb = g_plain_wpb.load(std::memory_order_relaxed);
+    uint64_t waves = std::min<uint64_t>(std::max<uint32_t>(a.n_tiles, 1u), plain_wave_cap(dev));
+    const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
+    const uint64_t total_waves = (uint64_t)blocks * wpb;
+    const uint64_t tiles_per_wave = (a.n_tiles + total_waves - 1) / total_waves;
+    return launch_plain(a, pick_k1(tiles_per_wave), blocks, wpb, st) == hipSuccess ? PPC_OK : PPC_EDEVICE;
+}
+
+// Per-wave counts are 32-bit: a wave adds at most 64 lanes x 2 dwords x 16
+// chunks = 2^11 per position per tile, so no wave may own more than 2^20
+// tiles in one launch (2^31 < 2^32).  Launches are cut so that
+// tiles <= waves x 2^20, and at 1 TiB to keep tile indices in 32 bits.
+static constexpr uint64_t kMaxTilesPerWave = 1ull << 20;
+static constexpr size_t kMaxLaunchBytes = (size_t)1 << 40;
+
+ppc_status plain_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, hipStream_t st) {
+    if (!(width == 8 || width == 16 || width == 32 || width == 64)) return PPC_EINVAL;
+    if (counts == nullptr || ((uintptr_t)counts & 7u) != 0) return PPC_EINVAL;
+    if (nbytes == 0) return PPC_OK;
+    if (buf == nullptr) return PPC_EINVAL;
+    const uint8_t *p = static_cast<const uint8_t *>(buf);
+    const uint32_t s = width / 8u;
+    const uint32_t m = (uint32_t)((uintptr_t)p % s);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
+    const size_t tile_bytes = (size_t)kTileChunks * 16u;
+    const size_t piece = std::min<size_t>(kMaxLaunchBytes,
+                                          (size_t)plain_wave_cap(dev) * kMaxTilesPerWave * tile_bytes);
+    size_t done = 0;
+    while (done < nbytes) {  // pieces start at multiples of 8 from buf: same m
+        const size_t len = std::min(piece, nbytes - done);
+        ppc_status rc = plain_launch_range(width, counts, p + done, len, m, st);
+        if (rc != PPC_OK) return rc;
+        done += len;
+    }
+    return PPC_OK;
+}
+
+}  // namespace ppc
+
+using namespace ppc;
+
+extern "C" {
+
+ppc_status ppc_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, void *stream) {
+    return plain_pospopcnt(width, counts, buf, nbytes, (hipStream_t)stream);
+}
+ppc_status ppc_pospopcnt8(uint64_t *counts, const void *buf, size_t nbytes, void *stream) {
+    return plain_pospopcnt(8, counts, buf, nbytes, (hipStream_t)stream);
+}
+ppc_status ppc_pospopcnt16(uint64_t *counts, const void *buf, size_t nbytes, void *stream) {
+    return plain_pospopcnt(16, counts, buf, nbytes, (hipStream_t)stream);
+}
+ppc_status ppc_pospopcnt32(uint64_t *counts, const void *buf, size_t nbytes, void *stream) {
+    return plain_pospopcnt(32, counts, buf, nbytes, (hipStream_t)stream);
+}
+ppc_status ppc_pospopcnt64(uint64_t *counts, const void *buf, size_t nbytes, void *stream) {
+    return plain_pospopcnt(64, counts, buf, nbytes, (hipStream_t)stream);
+}
+
+ppc_status ppc_set_plain_geometry(unsigned waves, unsigned waves_per_block) {
+    if (!(waves_per_block == 1 || waves_per_block == 2 || waves_per_block == 4 || waves_per_block == 8))
+        return PPC_EINVAL;
+    if (waves > (1u << 24)) return PPC_EINVAL;
+    g_plain_waves.store(waves);
+    g_plain_wpb.store(waves_per_block);
+    return PPC_OK;
+}
+
+ppc_status ppc_get_plain_geometry(unsigned *waves, unsigned *waves_per_block) {
+    if (!waves || !waves_per_block) return PPC_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
+    *waves = plain_wave_cap(dev);
+    *waves_per_block = g_plain_wpb.load();
+    return PPC_OK;
+}
+
+ppc_status ppc_read_roofline(uint64_t *sink, const void *buf, size_t nbytes, void *stream) {
+    if (sink == nullptr || ((uintptr_t)sink & 7u) != 0) return PPC_EINVAL;
+    if (nbytes == 0) return PPC_OK;
+    if (buf == nullptr || ((uintptr_t)buf & 15u) != 0 || (nbytes & 15u) != 0) return PPC_EINVAL;
+    if (nbytes % ((size_t)kTileChunks * 16u) != 0) return PPC_EINVAL;  // whole tiles only
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
+    const uint64_t n_tiles64 = nbytes / ((size_t)kTileChunks * 16u);
+    if (n_tiles64 >= (1ull << 32)) return PPC_EINVAL;
+    const uint32_t n_tiles = (uint32_t)n_tiles64;
+    const unsigned wpb = g_plain_wpb.load();
+    const uint64_t waves = std::min<uint64_t>(n_tiles, plain_wave_cap(dev));
+    const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
+    hipStream_t st = (hipStream_t)stream;
+    const uint4 *body = static_cast<const uint4 *>(buf);
+    auto *out = reinterpret_cast<unsigned long long *>(sink);
+    switch (wpb) {
+    case 1: hipLaunchKernelGGL(read_roofline_kernel<1>, dim3(blocks), dim3(64), 0, st, body, n_tiles, out); break;
+    case 2: hipLaunchKernelGGL(read_roofline_kernel<2>, dim3(blocks), dim3(128), 0, st, body, n_tiles, out); break;
+    case 4: hipLaunchKernelGGL(read_roofline_kernel<4>, dim3(blocks), dim3(256), 0, st, body, n_tiles, out); break;
+    default: hipLaunchKernelGGL(read_roofline_kernel<8>, dim3(blocks), dim3(512), 0, st, body, n_tiles, out); break;
+    }
+    return hipGetLastError() == hipSuccess ? PPC_OK : PPC_EDEVICE;
+}
+
+}  // extern "C"

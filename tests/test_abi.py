@@ -1,0 +1,76 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+* libppc.so loads and exports every function declared in include/*.h.
+* Argument validation that happens before any HIP call returns the
+  documented status codes.
+"""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(ppc_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2412_16370_amd as ppc
+
+    return ppc.lib()
+
+
+def test_header_declares_the_plain_calls():
+    names = declared_functions()
+    for w in (8, 16, 32, 64):
+        assert "ppc_pospopcnt%d" % w in names
+
+
+@pytest.mark.parametrize("name", declared_functions())
+def test_symbol_exported(lib, name):
+    assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in range(5):
+        assert lib.ppc_status_string(code)
+    assert lib.ppc_status_string(99) == b"PPC_UNKNOWN"
+
+
+def test_invalid_arguments_rejected_before_any_device_work(lib):
+    fake = 0x1000  # never dereferenced: validation fails first
+    assert lib.ppc_pospopcnt(12, fake, fake, 10, None) == 1
+    assert lib.ppc_pospopcnt(0, fake, fake, 10, None) == 1
+    assert lib.ppc_pospopcnt(16, None, fake, 10, None) == 1
+    assert lib.ppc_pospopcnt(16, fake + 4, fake, 10, None) == 1   # counts not 8-aligned
+    assert lib.ppc_pospopcnt16(None, fake, 10, None) == 1
+    assert lib.ppc_pospopcnt64(fake, None, 10, None) == 1         # NULL buf, nbytes > 0
+
+
+def test_empty_input_is_a_no_op(lib):
+    for w in (8, 16, 32, 64):
+        assert lib.ppc_pospopcnt(w, 0x1000, None, 0, None) == 0
+
+
+def test_plain_geometry_validation(lib):
+    assert lib.ppc_set_plain_geometry(0, 3) == 1
+    assert lib.ppc_set_plain_geometry(0, 16) == 1
+    assert lib.ppc_set_plain_geometry(1 << 25, 4) == 1
+    assert lib.ppc_set_plain_geometry(0, 4) == 0
+
+
+def test_roofline_validation(lib):
+    assert lib.ppc_read_roofline(None, 0x1000, 16384, None) == 1
+    assert lib.ppc_read_roofline(0x1000, 0x1001, 16384, None) == 1
+    assert lib.ppc_read_roofline(0x1000, 0x1000, 100, None) == 1
