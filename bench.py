@@ -108,6 +108,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short fixed run for rocprofv3: 3 plain calls per width, 3 read-roofline "
+                         "calls and 3 plain 256 MiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -128,6 +131,20 @@ def main():
     counts = {w: torch.zeros(w, dtype=torch.int64, device=dev) for w in WIDTHS}
     torch.cuda.synchronize()
     log("inputs resident: 4 x 256 MiB")
+
+    if args.profile:
+        sink = torch.zeros(1, dtype=torch.int64, device=dev)
+        dst = torch.empty(CALL_BYTES, dtype=torch.uint8, device=dev)
+        for i in range(3):
+            for j, w in enumerate(WIDTHS):
+                ppc.ppc_pospopcnt(w, counts[w], bufs[(i + j) % 4])
+        for i in range(3):
+            ppc.ppc_read_roofline(sink, bufs[i % 4])
+        for i in range(3):
+            dst.copy_(bufs[i % 4])
+        torch.cuda.synchronize()
+        log("profile run done")
+        return
 
     def step_calls(i0):
         for j, w in enumerate(WIDTHS):

@@ -71,9 +71,9 @@ ppc_status ppc_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size
 
 /* ------------------------------------------------------------------------
  * Launch geometry of the plain call.  `waves` caps the number of wavefronts
- * the grid holds (0 = the library default for the device); `waves_per_block`
- * is 1, 2, 4 or 8.  Applies to later plain calls from any thread on any
- * device.  Returns PPC_EINVAL for values out of range.
+ * the grid holds (0 = the library default: 8 per compute unit);
+ * `waves_per_block` is 2, 4 or 8 (default 8).  Applies to later plain calls
+ * from any thread on any device.  Returns PPC_EINVAL for values out of range.
  * ---------------------------------------------------------------------- */
 ppc_status ppc_set_plain_geometry(unsigned waves, unsigned waves_per_block);
 ppc_status ppc_get_plain_geometry(unsigned *waves, unsigned *waves_per_block);
@@ -83,8 +83,9 @@ ppc_status ppc_get_plain_geometry(unsigned *waves, unsigned *waves_per_block);
  * Table "Benchmarked algorithms"), which sums the input and adds the sum to
  * an output.  *sink (device, one uint64) += sum of the little-endian 64-bit
  * words of buf[0..nbytes) mod 2^64; `buf` must be 16-byte aligned and
- * nbytes a multiple of 16.  Same load pattern and launch geometry as the
- * plain pospopcnt call: it measures the bandwidth that call can reach.
+ * nbytes a multiple of 16 KiB (whole tiles).  Same load pattern and launch
+ * geometry as the plain pospopcnt call: it measures the bandwidth that call
+ * can reach.
  * ---------------------------------------------------------------------- */
 ppc_status ppc_read_roofline(uint64_t *sink, const void *buf, size_t nbytes, void *stream);
 

@@ -52,15 +52,19 @@ __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
 // Bit-plane accumulators of one lane: a1..a8 carry between tiles (the 4-bit
 // accumulator of Section 3.2); b[k] counts weight-16 planes in binary, so the
 // whole is one bit-sliced number with planes {a1,a2,a4,a8,b0,b1,...}.
-template <int K1>
+// A segment holds at most 2^kMaxK1 - 1 tiles, so b never overflows.
+constexpr int kMaxK1 = 6;
+constexpr uint32_t kSegTiles = (1u << kMaxK1) - 1u;  // 63 tiles = 1008 KiB per wave
+constexpr int kPlanes = 4 + kMaxK1;
+
 struct Planes {
     uint4 a1, a2, a4, a8;
-    uint4 b[K1];
+    uint4 b[kMaxK1];
 
     __device__ __forceinline__ void clear() {
         a1 = a2 = a4 = a8 = zero4();
 #pragma unroll
-        for (int k = 0; k < K1; ++k) b[k] = zero4();
+        for (int k = 0; k < kMaxK1; ++k) b[k] = zero4();
     }
 
     // CSA_{16+4}: (a1,a2,a4,a8) + 16 vectors -> (a16, a1,a2,a4,a8), 15 full
@@ -86,34 +90,24 @@ struct Planes {
         return sixteens;
     }
 
-    // b += a16 (bit-sliced ripple of half adders).  The caller bounds the
-    // number of additions per segment to 2^K1 - 1 so the top carry is 0.
-    __device__ __forceinline__ void add16(uint4 c) {
+    // b += a16 as the k-th addition of the segment (k = 1..kSegTiles): the
+    // counter is then at most k < 2^depth with depth = bit length of k, so
+    // the half-adder ripple stops at plane depth-1 with a zero carry.
+    // `depth` is wave-uniform: the skipped planes cost scalar branches only.
+    __device__ __forceinline__ void add16(uint4 c, uint32_t depth) {
 #pragma unroll
-        for (int k = 0; k < K1; ++k) {
-            uint4 t;
-            t.x = b[k].x & c.x; t.y = b[k].y & c.y; t.z = b[k].z & c.z; t.w = b[k].w & c.w;
-            b[k].x ^= c.x; b[k].y ^= c.y; b[k].z ^= c.z; b[k].w ^= c.w;
-            c = t;
+        for (int k = 0; k < kMaxK1; ++k) {
+            if ((uint32_t)k < depth) {
+                uint4 t;
+                t.x = b[k].x & c.x; t.y = b[k].y & c.y; t.z = b[k].z & c.z; t.w = b[k].w & c.w;
+                b[k].x ^= c.x; b[k].y ^= c.y; b[k].z ^= c.z; b[k].w ^= c.w;
+                c = t;
+            }
         }
-    }
-
-    // One more chunk of weight 1 (used for the head/tail bytes): a ripple
-    // through a1..a8 whose carry-out (weight 16) goes into b.
-    __device__ __forceinline__ void add1(uint4 v) {
-        uint4 *pl[4] = {&a1, &a2, &a4, &a8};
-        uint4 c = v;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            uint4 &p = *pl[k];
-            uint4 t;
-            t.x = p.x & c.x; t.y = p.y & c.y; t.z = p.z & c.z; t.w = p.w & c.w;
-            p.x ^= c.x; p.y ^= c.y; p.z ^= c.z; p.w ^= c.w;
-            c = t;
-        }
-        add16(c);
     }
 };
+
+__device__ __forceinline__ uint32_t bit_length(uint32_t k) { return 32u - (uint32_t)__builtin_clz(k | 1u) - (k == 0u ? 1u : 0u); }
 
 // ---- cross-lane helpers --------------------------------------------------
 // ds_swizzle in bit mode: lane j reads lane (j ^ x) inside its 32-lane half.
@@ -124,6 +118,12 @@ __device__ __forceinline__ uint32_t swz_xor(uint32_t v) {
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Index of the calling wave inside its block, as a wave-uniform (scalar)
+// value, so that loops and branches derived from it stay scalar.
+__device__ __forceinline__ uint32_t wave_in_block() {
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
 
 // One stage of a 32x32 bit-matrix transpose across the lanes of each 32-lane
 // half (the recursive block transpose of Section 4.4, done across lanes
@@ -168,63 +168,158 @@ __device__ __forceinline__ uint32_t column_popcount(uint32_t x, const TransposeC
 // End-of-segment reduction of a wave's bit planes into 64 integer counts
 // (the final accumulation of Section 4.4, rebuilt for a 64-lane wavefront).
 // Returns, in lane L, the number of set bits at address position L summed
-// over all lanes and all planes with their weights.  All 64 lanes must be
-// active.  E = number of planes, weights 1, 2, 4, ..., 2^(E-1).
+// over all lanes and planes with their weights.  All 64 lanes must be
+// active.  Plane e has weight 2^e; planes e >= e_used are zero (e_used is
+// wave-uniform) and are skipped.
 //   step A: inside each lane add dword x to z and y to w (same positions),
-//           as bit-sliced numbers -> E+1 planes for positions 0..31 (X) and
-//           32..63 (Y);
+//           as bit-sliced numbers -> planes for positions 0..31 (X) and
+//           32..63 (Y), one plane more;
 //   step B: lanes L < 32 take X from lane L+32, lanes L >= 32 take Y from
-//           lane L-32, and add -> E+2 planes, one dword each;
+//           lane L-32 (one permlane32 swap per plane), and add -> one plane
+//           more again, one dword per plane;
 //   step C: per plane, a 32x32 cross-lane transpose and a popcount.
-template <int E>
-__device__ __forceinline__ uint32_t wave_position_counts(const uint4 (&p)[E]) {
-    uint32_t X[E + 1], Y[E + 1];
+__device__ __forceinline__ uint32_t wave_position_counts(const uint4 (&p)[kPlanes], uint32_t e_used) {
+    uint32_t X[kPlanes + 1], Y[kPlanes + 1];
     {
         uint32_t cx = 0, cy = 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
+        for (int e = 0; e < kPlanes; ++e) {
             X[e] = parity3(p[e].x, p[e].z, cx);
-            uint32_t ncx = majority3(p[e].x, p[e].z, cx);
             Y[e] = parity3(p[e].y, p[e].w, cy);
-            uint32_t ncy = majority3(p[e].y, p[e].w, cy);
+            const uint32_t ncx = majority3(p[e].x, p[e].z, cx);
+            const uint32_t ncy = majority3(p[e].y, p[e].w, cy);
             cx = ncx;
             cy = ncy;
         }
-        X[E] = cx;
-        Y[E] = cy;
+        X[kPlanes] = cx;
+        Y[kPlanes] = cy;
     }
-    const bool low_half = lane_id() < 32;
-    uint32_t Z[E + 2];
+    uint32_t Z[kPlanes + 2];
     {
         uint32_t c = 0;
 #pragma unroll
-        for (int e = 0; e <= E; ++e) {
-            uint32_t keep = low_half ? X[e] : Y[e];
-            uint32_t send = low_half ? Y[e] : X[e];
-            uint32_t recv = (uint32_t)__shfl_xor((int)send, 32);
-            Z[e] = parity3(keep, recv, c);
-            c = majority3(keep, recv, c);
+        for (int e = 0; e <= kPlanes; ++e) {
+            if ((uint32_t)e <= e_used) {
+                // after the swap: lo = X (lanes < 32) / Y of lane-32 (lanes >= 32),
+                //                 hi = X of lane+32 (lanes < 32) / Y (lanes >= 32)
+                const auto sw = __builtin_amdgcn_permlane32_swap(X[e], Y[e], false, false);
+                const uint32_t lo = sw[0], hi = sw[1];
+                Z[e] = parity3(lo, hi, c);
+                c = majority3(lo, hi, c);
+            } else if ((uint32_t)e == e_used + 1u) {
+                Z[e] = c;  // the carry out of the top used plane
+                c = 0;
+            } else {
+                Z[e] = 0;
+            }
         }
-        Z[E + 1] = c;
+        Z[kPlanes + 1] = c;  // nonzero only when every plane is in use
     }
     const TransposeConsts tc;
     uint32_t total = 0;
 #pragma unroll
-    for (int e = 0; e < E + 2; ++e) total += column_popcount(Z[e], tc) << e;
+    for (int e = 0; e < kPlanes + 2; ++e)
+        if ((uint32_t)e < e_used + 2u) total += column_popcount(Z[e], tc) << e;
     return total;
 }
 
-// Bit-plane reduction of one lane's planes, packaged for the kernels.
-template <int K1>
-__device__ __forceinline__ uint32_t planes_position_counts(const Planes<K1> &pl) {
-    uint4 p[4 + K1];
+__device__ __forceinline__ uint32_t planes_position_counts(const Planes &pl, uint32_t b_used) {
+    uint4 p[kPlanes];
     p[0] = pl.a1;
     p[1] = pl.a2;
     p[2] = pl.a4;
     p[3] = pl.a8;
 #pragma unroll
-    for (int k = 0; k < K1; ++k) p[4 + k] = pl.b[k];
-    return wave_position_counts<4 + K1>(p);
+    for (int k = 0; k < kMaxK1; ++k) p[4 + k] = pl.b[k];
+    return wave_position_counts(p, 4u + b_used);
+}
+
+// Streaming (non-temporal) 16-byte load: the input is read exactly once, so
+// it is marked as not worth keeping in the caches.
+__device__ __forceinline__ uint4 load_stream(const uint4 *p) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 r = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    return make_uint4(r.x, r.y, r.z, r.w);
+}
+
+template <bool NT>
+__device__ __forceinline__ void load_tile(uint4 (&v)[kLoadsPerTile], const uint4 *p) {
+#pragma unroll
+    for (int j = 0; j < kLoadsPerTile; ++j) v[j] = NT ? load_stream(p + j * kWave) : p[j * kWave];
+}
+
+// One wave's share of a body of 16-byte chunks: tiles t0, t0+stride, ... that
+// are < t_end.  Tiles below n_full are whole (1024 chunks); the tile n_full,
+// if walked, is the partial last tile and its loads are predicated on
+// chunk < n_chunks.  `edge` is one extra weight-1 chunk (head/tail bytes,
+// zero if none).  Returns lane L = count at address position L.
+//
+// Software pipeline: two register sets take turns, and the steady-state
+// loop issues the next tile's 16 loads unconditionally before compressing
+// the current tile, so the compiler's wait counts let those loads stay in
+// flight (a conditional load there makes it wait for them).  The last one
+// or two whole tiles are peeled off after the loop.
+template <bool NT>
+__device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t n_chunks, uint32_t n_full,
+                                                     uint32_t t0, uint32_t t_end, uint32_t stride, uint4 edge,
+                                                     bool has_edge) {
+    const uint32_t lane = __lane_id();
+    Planes pl;
+    pl.clear();
+    pl.a1 = edge;
+    bool any = has_edge;
+    uint32_t acc = 0, seg = 0;
+    const uint32_t full_end = t_end < n_full ? t_end : n_full;
+    // number of whole tiles this wave walks (wave-uniform)
+    const uint32_t n_mine = t0 < full_end ? (full_end - t0 + stride - 1) / stride : 0u;
+    auto tile_ptr = [&](uint32_t i) { return body + (uint64_t)(t0 + i * stride) * kTileChunks + lane; };
+    auto add_tile = [&](const uint4 (&v)[kLoadsPerTile]) {
+        ++seg;
+        pl.add16(pl.csa16(v), bit_length(seg));
+    };
+    constexpr uint32_t kFlushAt = kSegTiles - 1u;  // even, <= 63: checked once per pair
+    if (n_mine > 0) {
+        any = true;
+        uint4 va[kLoadsPerTile], vb[kLoadsPerTile];
+        load_tile<NT>(va, tile_ptr(0));
+        uint32_t i = 0;
+        while (i + 2u < n_mine) {  // tiles i (in va), i+1, i+2 exist
+            load_tile<NT>(vb, tile_ptr(i + 1u));
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the math
+            add_tile(va);
+            load_tile<NT>(va, tile_ptr(i + 2u));
+            __builtin_amdgcn_sched_barrier(0);
+            add_tile(vb);
+            i += 2u;
+            if (seg >= kFlushAt) {
+                acc += planes_position_counts(pl, kMaxK1);
+                pl.clear();
+                seg = 0;
+            }
+        }
+        if (i + 1u < n_mine) {  // two tiles left: i in va, i+1
+            load_tile<NT>(vb, tile_ptr(i + 1u));
+            __builtin_amdgcn_sched_barrier(0);
+            add_tile(va);
+            add_tile(vb);
+        } else {
+            add_tile(va);
+        }
+    }
+    uint32_t t = t0 + n_mine * stride;  // first walked tile at or past full_end
+    if (t < t_end && t == n_full && (uint64_t)n_full * kTileChunks < n_chunks) {
+        uint4 v[kLoadsPerTile];
+        const uint64_t base = (uint64_t)t * kTileChunks + lane;
+#pragma unroll
+        for (int j = 0; j < kLoadsPerTile; ++j) {
+            const uint64_t idx = base + (uint64_t)j * kWave;
+            v[j] = idx < n_chunks ? body[idx] : zero4();
+        }
+        add_tile(v);
+        any = true;
+    }
+    if (any) acc += planes_position_counts(pl, bit_length(seg));
+    return acc;
 }
 
 // The byte at address `a` (value `byte`) as a chunk holding only that byte

@@ -10,9 +10,9 @@
 //                tile every lane runs the CSA_{16+4} network (Section 4.2)
 //                and adds the weight-16 plane to a bit-sliced counter
 //                (the role of the intermediate accumulation, Section 4.3).
-//   overflow   : a segment holds at most 2^K1 - 1 tiles so the bit-sliced
+//   overflow   : a segment holds at most 63 tiles so the 6-plane bit-sliced
 //                counter cannot overflow (Section 4.3's flush rule, with the
-//                bound proven at compile time instead of tracked at run time).
+//                bound fixed at compile time instead of tracked at run time).
 //   final acc. : planes -> 64 integer counts per wave by cross-lane
 //                transposes and popcounts (Section 4.4).
 //   f_w        : per-block LDS partials are folded to w positions relative
@@ -42,60 +42,27 @@ struct PlainArgs {
     uint32_t m;                 // buf mod (w/8)
 };
 
-__device__ __forceinline__ void load_tile(uint4 (&v)[kLoadsPerTile], const uint4 *p) {
-#pragma unroll
-    for (int j = 0; j < kLoadsPerTile; ++j) v[j] = p[j * kWave];
-}
-
-template <int K1, int WPB>
+// WPB: waves per block; NT: streaming loads (large inputs).  Each wave
+// walks tiles gw, gw + nw, ... (nw = waves in the grid), so one load
+// instruction of a wave reads 1 KiB and the 16 loads of a tile 16 KiB, all
+// contiguous; at any moment the grid works on one contiguous window.
+template <int WPB, bool NT>
 __global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
-    constexpr uint32_t kSeg = (1u << K1) - 1u;
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wib = threadIdx.x / kWave;
+    const uint32_t wib = wave_in_block();
     const uint32_t gw = blockIdx.x * WPB + wib;
     const uint32_t nw = gridDim.x * WPB;
 
-    Planes<K1> pl;
-    pl.clear();
-    uint32_t acc = 0;
-    bool any = false;
-
-    if (gw == 0) {  // head and tail bytes, one per lane
-        uint4 e = zero4();
+    uint4 edge = zero4();
+    if (gw == 0) {  // head and tail bytes, one per lane, read bytewise
         if (lane < 32) {
-            if (lane < a.edge0_len) e = byte_as_chunk((uint64_t)(a.edge0 + lane), a.edge0[lane]);
+            if (lane < a.edge0_len) edge = byte_as_chunk((uint64_t)(a.edge0 + lane), a.edge0[lane]);
         } else if (lane - 32 < a.edge1_len) {
-            e = byte_as_chunk((uint64_t)(a.edge1 + (lane - 32)), a.edge1[lane - 32]);
-        }
-        pl.a1 = e;
-        any = true;
-    }
-
-    uint32_t seg = 0;
-    uint32_t t = gw;
-    for (; t < a.n_full_tiles; t += nw) {
-        uint4 v[kLoadsPerTile];
-        load_tile(v, a.body + (uint64_t)t * kTileChunks + lane);
-        pl.add16(pl.csa16(v));
-        any = true;
-        if (++seg == kSeg) {
-            acc += planes_position_counts<K1>(pl);
-            pl.clear();
-            seg = 0;
+            edge = byte_as_chunk((uint64_t)(a.edge1 + (lane - 32)), a.edge1[lane - 32]);
         }
     }
-    if (t < a.n_tiles) {  // the one partial tile, loads predicated
-        uint4 v[kLoadsPerTile];
-        const uint64_t base = (uint64_t)t * kTileChunks + lane;
-#pragma unroll
-        for (int j = 0; j < kLoadsPerTile; ++j) {
-            const uint64_t idx = base + (uint64_t)j * kWave;
-            v[j] = idx < a.n_chunks ? a.body[idx] : zero4();
-        }
-        pl.add16(pl.csa16(v));
-        any = true;
-    }
-    if (any) acc += planes_position_counts<K1>(pl);
+    const uint32_t acc =
+        wave_count_tiles<NT>(a.body, a.n_chunks, a.n_full_tiles, gw, a.n_tiles, nw, edge, gw == 0);
 
     __shared__ uint32_t part[WPB][kWave];
     part[wib][lane] = acc;
@@ -113,65 +80,91 @@ __global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
     }
 }
 
-// Read roofline: same tiles, same loads; sums the 64-bit words.
+// Read roofline: same tiles, same streaming loads and the same next-tile
+// prefetch as the pospopcnt kernel; sums the 64-bit words instead of
+// counting bits.
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void load_tile_u64(u64x2 (&v)[kLoadsPerTile], const uint4 *p) {
+#pragma unroll
+    for (int j = 0; j < kLoadsPerTile; ++j)
+        v[j] = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(p + j * kWave));
+}
+
 template <int WPB>
 __global__ __launch_bounds__(WPB *kWave) void read_roofline_kernel(const uint4 *body, uint32_t n_tiles,
                                                                    unsigned long long *sink) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t gw = blockIdx.x * WPB + threadIdx.x / kWave;
+    const uint32_t gw = blockIdx.x * WPB + wave_in_block();
     const uint32_t nw = gridDim.x * WPB;
-    uint64_t s0 = 0, s1 = 0;
-    for (uint32_t t = gw; t < n_tiles; t += nw) {
-        uint4 v[kLoadsPerTile];
-        load_tile(v, body + (uint64_t)t * kTileChunks + lane);
+    u64x2 acc = {0, 0};
+    const uint32_t n_mine = gw < n_tiles ? (n_tiles - gw + nw - 1) / nw : 0u;
+    auto tile_ptr = [&](uint32_t i) { return body + (uint64_t)(gw + i * nw) * kTileChunks + lane; };
+    if (n_mine > 0) {
+        u64x2 va[kLoadsPerTile], vb[kLoadsPerTile];
+        load_tile_u64(va, tile_ptr(0));
+        uint32_t i = 0;
+        while (i + 2u < n_mine) {
+            load_tile_u64(vb, tile_ptr(i + 1u));
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the math
 #pragma unroll
-        for (int j = 0; j < kLoadsPerTile; ++j) {
-            s0 += ((uint64_t)v[j].y << 32) | v[j].x;
-            s1 += ((uint64_t)v[j].w << 32) | v[j].z;
+            for (int j = 0; j < kLoadsPerTile; ++j) acc += va[j];
+            load_tile_u64(va, tile_ptr(i + 2u));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < kLoadsPerTile; ++j) acc += vb[j];
+            i += 2u;
+        }
+        if (i + 1u < n_mine) {
+            load_tile_u64(vb, tile_ptr(i + 1u));
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < kLoadsPerTile; ++j) acc += va[j] + vb[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < kLoadsPerTile; ++j) acc += va[j];
         }
     }
-    uint64_t s = s0 + s1;
+    uint64_t s = acc.x + acc.y;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-    if (lane == 0 && s) atomicAdd(sink, (unsigned long long)s);
+    __shared__ uint64_t part[WPB];
+    if (lane == 0) part[threadIdx.x / kWave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t b = 0;
+#pragma unroll
+        for (int wv = 0; wv < WPB; ++wv) b += part[wv];
+        if (b) atomicAdd(sink, (unsigned long long)b);
+    }
 }
 
 // ---- host side -----------------------------------------------------------
 static std::atomic<unsigned> g_plain_waves{0};        // 0 = default
-static std::atomic<unsigned> g_plain_wpb{4};
+static std::atomic<unsigned> g_plain_wpb{8};
 
-template <int K1>
-static hipError_t launch_plain_k(const PlainArgs &a, unsigned blocks, unsigned wpb, hipStream_t st) {
-    switch (wpb) {
-    case 1: hipLaunchKernelGGL((pospop_plain_kernel<K1, 1>), dim3(blocks), dim3(64), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((pospop_plain_kernel<K1, 2>), dim3(blocks), dim3(128), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((pospop_plain_kernel<K1, 4>), dim3(blocks), dim3(256), 0, st, a); break;
-    default: hipLaunchKernelGGL((pospop_plain_kernel<K1, 8>), dim3(blocks), dim3(512), 0, st, a); break;
-    }
+// Inputs at least this large use streaming loads.
+static constexpr size_t kStreamBytes = (size_t)32 << 20;
+
+template <bool NT>
+static hipError_t launch_plain_nt(const PlainArgs &a, unsigned blocks, unsigned wpb, hipStream_t st) {
+    if (wpb == 2)
+        hipLaunchKernelGGL((pospop_plain_kernel<2, NT>), dim3(blocks), dim3(128), 0, st, a);
+    else if (wpb == 4)
+        hipLaunchKernelGGL((pospop_plain_kernel<4, NT>), dim3(blocks), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((pospop_plain_kernel<8, NT>), dim3(blocks), dim3(512), 0, st, a);
     return hipGetLastError();
 }
 
-static hipError_t launch_plain(const PlainArgs &a, int k1, unsigned blocks, unsigned wpb, hipStream_t st) {
-    switch (k1) {
-    case 1: return launch_plain_k<1>(a, blocks, wpb, st);
-    case 2: return launch_plain_k<2>(a, blocks, wpb, st);
-    case 3: return launch_plain_k<3>(a, blocks, wpb, st);
-    case 4: return launch_plain_k<4>(a, blocks, wpb, st);
-    default: return launch_plain_k<5>(a, blocks, wpb, st);
-    }
-}
-
-// Smallest K1 whose segment (2^K1 - 1 tiles) covers a wave's share.
-static int pick_k1(uint64_t tiles_per_wave) {
-    int k1 = 1;
-    while (k1 < 5 && ((1ull << k1) - 1ull) < tiles_per_wave) ++k1;
-    return k1;
+static hipError_t launch_plain(const PlainArgs &a, bool nt, unsigned blocks, unsigned wpb, hipStream_t st) {
+    return nt ? launch_plain_nt<true>(a, blocks, wpb, st) : launch_plain_nt<false>(a, blocks, wpb, st);
 }
 
 unsigned plain_wave_cap(int device) {
     unsigned w = g_plain_waves.load(std::memory_order_relaxed);
     if (w) return w;
-    return (unsigned)device_cus(device) * 8u;  // two waves per SIMD
+    return (unsigned)device_cus(device) * 8u;  // one 8-wave block per CU
 }
 
 // One launch over a range the caller has sized with kMaxTilesPerWave.
@@ -207,9 +200,7 @@ static ppc_status plain_launch_range(unsigned width, uint64_t *counts, const uin
     const unsigned wpb = g_plain_wpb.load(std::memory_order_relaxed);
     uint64_t waves = std::min<uint64_t>(std::max<uint32_t>(a.n_tiles, 1u), plain_wave_cap(dev));
     const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
-    const uint64_t total_waves = (uint64_t)blocks * wpb;
-    const uint64_t tiles_per_wave = (a.n_tiles + total_waves - 1) / total_waves;
-    return launch_plain(a, pick_k1(tiles_per_wave), blocks, wpb, st) == hipSuccess ? PPC_OK : PPC_EDEVICE;
+    return launch_plain(a, nbytes >= kStreamBytes, blocks, wpb, st) == hipSuccess ? PPC_OK : PPC_EDEVICE;
 }
 
 // Per-wave counts are 32-bit: a wave adds at most 64 lanes x 2 dwords x 16
@@ -265,8 +256,7 @@ ppc_status ppc_pospopcnt64(uint64_t *counts, const void *buf, size_t nbytes, voi
 }
 
 ppc_status ppc_set_plain_geometry(unsigned waves, unsigned waves_per_block) {
-    if (!(waves_per_block == 1 || waves_per_block == 2 || waves_per_block == 4 || waves_per_block == 8))
-        return PPC_EINVAL;
+    if (!(waves_per_block == 2 || waves_per_block == 4 || waves_per_block == 8)) return PPC_EINVAL;
     if (waves > (1u << 24)) return PPC_EINVAL;
     g_plain_waves.store(waves);
     g_plain_wpb.store(waves_per_block);
@@ -298,12 +288,12 @@ ppc_status ppc_read_roofline(uint64_t *sink, const void *buf, size_t nbytes, voi
     hipStream_t st = (hipStream_t)stream;
     const uint4 *body = static_cast<const uint4 *>(buf);
     auto *out = reinterpret_cast<unsigned long long *>(sink);
-    switch (wpb) {
-    case 1: hipLaunchKernelGGL(read_roofline_kernel<1>, dim3(blocks), dim3(64), 0, st, body, n_tiles, out); break;
-    case 2: hipLaunchKernelGGL(read_roofline_kernel<2>, dim3(blocks), dim3(128), 0, st, body, n_tiles, out); break;
-    case 4: hipLaunchKernelGGL(read_roofline_kernel<4>, dim3(blocks), dim3(256), 0, st, body, n_tiles, out); break;
-    default: hipLaunchKernelGGL(read_roofline_kernel<8>, dim3(blocks), dim3(512), 0, st, body, n_tiles, out); break;
-    }
+    if (wpb == 2)
+        hipLaunchKernelGGL(read_roofline_kernel<2>, dim3(blocks), dim3(128), 0, st, body, n_tiles, out);
+    else if (wpb == 4)
+        hipLaunchKernelGGL(read_roofline_kernel<4>, dim3(blocks), dim3(256), 0, st, body, n_tiles, out);
+    else
+        hipLaunchKernelGGL(read_roofline_kernel<8>, dim3(blocks), dim3(512), 0, st, body, n_tiles, out);
     return hipGetLastError() == hipSuccess ? PPC_OK : PPC_EDEVICE;
 }
 

@@ -65,9 +65,12 @@ def test_empty_input_is_a_no_op(lib):
 
 def test_plain_geometry_validation(lib):
     assert lib.ppc_set_plain_geometry(0, 3) == 1
+    assert lib.ppc_set_plain_geometry(0, 1) == 1
+    assert lib.ppc_set_plain_geometry(0, 2) == 0
     assert lib.ppc_set_plain_geometry(0, 16) == 1
     assert lib.ppc_set_plain_geometry(1 << 25, 4) == 1
     assert lib.ppc_set_plain_geometry(0, 4) == 0
+    assert lib.ppc_set_plain_geometry(0, 8) == 0
 
 
 def test_roofline_validation(lib):

@@ -41,7 +41,7 @@ def ppc():
 @pytest.fixture
 def geometry(ppc):
     saved = ppc.ppc_get_plain_geometry()
-    ppc.ppc_set_plain_geometry(0, 4)
+    ppc.ppc_set_plain_geometry(0, 8)
     yield ppc
     ppc.ppc_set_plain_geometry(0, saved[1])
 
@@ -140,13 +140,13 @@ def test_onehot_64MiB_equals_histogram(geometry):
         assert np.array_equal(got.reshape(w // 8, 8).sum(axis=0), hist)
 
 
-@pytest.mark.parametrize("waves,wpb", [(1, 1), (3, 1), (64, 2), (1000, 8), (4096, 4)])
+@pytest.mark.parametrize("waves,wpb", [(1, 2), (3, 4), (64, 8), (700, 2), (1000, 8), (4096, 4), (20000, 8)])
 def test_small_grids_force_many_segments(geometry, waves, wpb):
     ppc = geometry
     ppc.ppc_set_plain_geometry(waves, wpb)
     host = synth.random_bytes((32 << 20) + 77, seed=waves)
     buf = torch.from_numpy(host).to(dev())
-    for w, off in ((8, 0), (64, 9)):
+    for w, off in ((8, 0), (64, 9)):  # below and above the streaming-load size
         got = run(ppc, w, buf[off:])
         assert np.array_equal(got, oracle.pospopcnt_mt(host[off:], w, HOST_THREADS))
 
