@@ -89,6 +89,142 @@ ppc_status ppc_get_plain_geometry(unsigned *waves, unsigned *waves_per_block);
  * ---------------------------------------------------------------------- */
 ppc_status ppc_read_roofline(uint64_t *sink, const void *buf, size_t nbytes, void *stream);
 
+
+/* ------------------------------------------------------------------------
+ * Batched form: thousands of arrays of uneven length and mixed width in one
+ * persistent launch.  Same arithmetic as the plain call for every array
+ * (the width only selects the final accumulation, Section 5), so each
+ * array's counts are exactly what ppc_pospopcnt would add.
+ * ---------------------------------------------------------------------- */
+typedef struct ppc_desc {
+    const void *buf;   /* device pointer, any alignment                     */
+    uint64_t nbytes;   /* bytes to count (0 allowed)                        */
+    uint64_t *counts;  /* device pointer to `width` uint64, 8-byte aligned  */
+    uint32_t width;    /* 8, 16, 32 or 64                                   */
+    uint32_t reserved; /* must be 0                                         */
+} ppc_desc;
+
+typedef struct ppc_plan_opts {
+    uint32_t tiles_per_item; /* 16 KiB tiles per work item; 0 = tuned        */
+    uint32_t waves;          /* wavefronts in the persistent grid; 0 = tuned */
+    uint32_t autotune;       /* 1: time candidates when not cached/given    */
+    uint32_t use_graph;      /* 1: replay a captured hipGraph on run         */
+    uint32_t reserved;       /* must be 0                                    */
+} ppc_plan_opts;
+
+typedef struct ppc_plan_info {
+    uint64_t n_arrays, n_items, total_bytes;
+    uint32_t tiles_per_item, waves;
+    uint32_t tuned; /* 0 = given or default, 1 = measured now, 2 = from cache */
+    uint32_t graph; /* 1 if runs replay a hipGraph                            */
+} ppc_plan_info;
+
+typedef struct ppc_plan ppc_plan;
+
+/* Builds a plan for `n` arrays described by the HOST array `descs` (the
+ * descriptors are copied; the buffers and counters they point to must stay
+ * valid while the plan is used).  Validates every descriptor (PPC_EINVAL if
+ * any is bad: same rules as the plain call), splits arrays into work items,
+ * picks tiles per item and grid size (opts NULL = autotune + graph), uploads
+ * the tables and captures the launch.  Autotuning times candidate settings
+ * on `stream` with the counters redirected to scratch memory, so the
+ * caller's counters are untouched; the choice is cached in the text file
+ * $PPC_TUNE_CACHE (default ~/.cache/ppc_tune.txt) keyed by device and batch
+ * shape.  Blocks until the plan is ready.  *plan is owned by the caller and
+ * released with ppc_plan_destroy. */
+ppc_status ppc_plan_create(ppc_plan **plan, const ppc_desc *descs, size_t n, const ppc_plan_opts *opts,
+                           void *stream);
+
+/* Enqueues one pass over every array of the plan on `stream`: each array's
+ * counts are added to its counters.  Runs of one plan must not overlap
+ * (they share the plan's work cursor): order them on one stream. */
+ppc_status ppc_plan_run(ppc_plan *plan, void *stream);
+
+ppc_status ppc_plan_get_info(const ppc_plan *plan, ppc_plan_info *info);
+
+/* Waits for the device to be idle, then frees the plan. */
+ppc_status ppc_plan_destroy(ppc_plan *plan);
+
+/* ------------------------------------------------------------------------
+ * Serving form: count queries over device-resident columns.  A pool of
+ * equal columns (pool_bytes = n_columns * column_bytes, device memory owned
+ * by the caller) is counted by requests (column, width, offset, nbytes).
+ * Admission is by memory: a request is admitted when a result slot is free
+ * and the bytes of all admitted, unfinished requests stay within
+ * `inflight_bytes` (a request larger than the budget is admitted only when
+ * nothing else is in flight).  Admitted requests are batched continuously:
+ * whenever one of `n_streams` streams is idle and requests are pending,
+ * the pending ones (up to `max_batch`, in arrival order) go out as one
+ * persistent batched launch, so batches overlap on the device.  Results are
+ * exactly the plain call's counts for the same bytes and width.  A server
+ * is used from one host thread at a time.
+ * ---------------------------------------------------------------------- */
+typedef struct ppc_server_cfg {
+    uint32_t n_streams;      /* batches in flight at once (0 = 4)             */
+    uint32_t max_batch;      /* requests per batch (0 = 1024)                 */
+    uint32_t max_inflight;   /* result slots = admitted requests (0 = 16384)  */
+    uint32_t tiles_per_item; /* 16 KiB tiles per work item (0 = 16)           */
+    uint64_t inflight_bytes; /* admission budget in bytes (0 = 4 GiB)         */
+    uint32_t waves;          /* persistent grid per batch (0 = 8 per CU)      */
+    uint32_t reserved;       /* must be 0                                     */
+} ppc_server_cfg;
+
+typedef struct ppc_request {
+    uint32_t column; /* column index                         */
+    uint32_t width;  /* 8, 16, 32 or 64                      */
+    uint64_t offset; /* byte offset inside the column        */
+    uint64_t nbytes; /* byte length; offset+nbytes <= column */
+    uint64_t tag;    /* caller's id, returned in the result  */
+} ppc_request;
+
+typedef struct ppc_result {
+    uint64_t tag;
+    uint32_t width;
+    uint32_t status;      /* PPC_OK, or PPC_EDEVICE if its batch failed */
+    uint64_t t_submit_ns; /* admission time (steady clock)            */
+    uint64_t t_done_ns;   /* time the host saw the counts             */
+    uint64_t counts[64];  /* counts[0..width) valid                   */
+} ppc_result;
+
+typedef struct ppc_server_stats {
+    uint64_t inflight, pending, inflight_bytes;
+    uint64_t batches, batched_requests, max_batch_seen;
+} ppc_server_stats;
+
+typedef struct ppc_trace_stats {
+    uint64_t n_requests, total_bytes, makespan_ns;
+    uint64_t p50_ns, p99_ns, max_ns, mean_ns; /* arrival -> counts on host */
+    uint64_t batches, busy_rejections;
+    double mean_batch;
+    double gbps; /* total_bytes / makespan, 1 GB = 1e9 B */
+} ppc_trace_stats;
+
+typedef struct ppc_server ppc_server;
+
+ppc_status ppc_server_create(ppc_server **server, const void *pool, uint64_t pool_bytes, uint64_t column_bytes,
+                             const ppc_server_cfg *cfg);
+
+/* Admits one request (PPC_EBUSY if slots or the byte budget are exhausted:
+ * poll and retry; PPC_EINVAL if it lies outside its column or the width is
+ * bad) and makes progress (retires finished batches, launches pending). */
+ppc_status ppc_server_submit(ppc_server *server, const ppc_request *req);
+
+/* Makes progress and returns up to `cap` finished results in *out. */
+ppc_status ppc_server_poll(ppc_server *server, ppc_result *out, size_t cap, size_t *n_out);
+
+ppc_status ppc_server_get_stats(const ppc_server *server, ppc_server_stats *stats);
+
+/* Open-loop driver: request i arrives arrival_ns[i] nanoseconds after the
+ * start (non-decreasing); requests not admitted wait in arrival order.
+ * results[i] receives request i's result (its tag is i) and *stats the
+ * latency percentiles (arrival -> counts on host) and throughput.  The
+ * server must be idle (nothing admitted, nothing unpolled). */
+ppc_status ppc_server_run_trace(ppc_server *server, const ppc_request *reqs, const uint64_t *arrival_ns, size_t n,
+                                ppc_result *results, ppc_trace_stats *stats);
+
+/* Waits for the server's streams, then frees it. */
+ppc_status ppc_server_destroy(ppc_server *server);
+
 #ifdef __cplusplus
 }
 #endif

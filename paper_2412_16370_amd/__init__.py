@@ -30,6 +30,54 @@ class PpcError(RuntimeError):
 
 _lib = None
 
+
+class ppc_desc(ctypes.Structure):
+    _fields_ = [("buf", ctypes.c_void_p), ("nbytes", ctypes.c_uint64), ("counts", ctypes.c_void_p),
+                ("width", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class ppc_plan_opts(ctypes.Structure):
+    _fields_ = [("tiles_per_item", ctypes.c_uint32), ("waves", ctypes.c_uint32),
+                ("autotune", ctypes.c_uint32), ("use_graph", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ppc_plan_info(ctypes.Structure):
+    _fields_ = [("n_arrays", ctypes.c_uint64), ("n_items", ctypes.c_uint64),
+                ("total_bytes", ctypes.c_uint64), ("tiles_per_item", ctypes.c_uint32),
+                ("waves", ctypes.c_uint32), ("tuned", ctypes.c_uint32), ("graph", ctypes.c_uint32)]
+
+
+class ppc_server_cfg(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("max_inflight", ctypes.c_uint32), ("tiles_per_item", ctypes.c_uint32),
+                ("inflight_bytes", ctypes.c_uint64), ("waves", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class ppc_request(ctypes.Structure):
+    _fields_ = [("column", ctypes.c_uint32), ("width", ctypes.c_uint32), ("offset", ctypes.c_uint64),
+                ("nbytes", ctypes.c_uint64), ("tag", ctypes.c_uint64)]
+
+
+class ppc_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("width", ctypes.c_uint32), ("status", ctypes.c_uint32),
+                ("t_submit_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
+                ("counts", ctypes.c_uint64 * 64)]
+
+
+class ppc_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("inflight", "pending", "inflight_bytes", "batches",
+                                                "batched_requests", "max_batch_seen")]
+
+
+class ppc_trace_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("n_requests", "total_bytes", "makespan_ns", "p50_ns",
+                                                "p99_ns", "max_ns", "mean_ns", "batches",
+                                                "busy_rejections")] + \
+               [("mean_batch", ctypes.c_double), ("gbps", ctypes.c_double)]
+
+
 _c_size = ctypes.c_size_t
 _c_ptr = ctypes.c_void_p
 _c_uint = ctypes.c_uint
@@ -47,6 +95,21 @@ def _declare(lib):
         "ppc_set_plain_geometry": ([_c_uint, _c_uint], ctypes.c_int),
         "ppc_get_plain_geometry": ([ctypes.POINTER(_c_uint), ctypes.POINTER(_c_uint)], ctypes.c_int),
         "ppc_read_roofline": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
+        "ppc_plan_create": ([ctypes.POINTER(_c_ptr), ctypes.POINTER(ppc_desc), _c_size,
+                             ctypes.POINTER(ppc_plan_opts), _c_ptr], ctypes.c_int),
+        "ppc_plan_run": ([_c_ptr, _c_ptr], ctypes.c_int),
+        "ppc_plan_get_info": ([_c_ptr, ctypes.POINTER(ppc_plan_info)], ctypes.c_int),
+        "ppc_plan_destroy": ([_c_ptr], ctypes.c_int),
+        "ppc_server_create": ([ctypes.POINTER(_c_ptr), _c_ptr, ctypes.c_uint64, ctypes.c_uint64,
+                               ctypes.POINTER(ppc_server_cfg)], ctypes.c_int),
+        "ppc_server_submit": ([_c_ptr, ctypes.POINTER(ppc_request)], ctypes.c_int),
+        "ppc_server_poll": ([_c_ptr, ctypes.POINTER(ppc_result), _c_size, ctypes.POINTER(_c_size)],
+                            ctypes.c_int),
+        "ppc_server_get_stats": ([_c_ptr, ctypes.POINTER(ppc_server_stats)], ctypes.c_int),
+        "ppc_server_run_trace": ([_c_ptr, ctypes.POINTER(ppc_request), ctypes.POINTER(ctypes.c_uint64),
+                                  _c_size, ctypes.POINTER(ppc_result), ctypes.POINTER(ppc_trace_stats)],
+                                 ctypes.c_int),
+        "ppc_server_destroy": ([_c_ptr], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -151,6 +214,96 @@ def ppc_get_plain_geometry() -> tuple[int, int]:
 def ppc_read_roofline(sink, buf, nbytes=None, stream=None):
     _check(lib().ppc_read_roofline(_ptr(sink), _ptr(buf), _nbytes(buf, nbytes), _stream(stream)),
            "ppc_read_roofline")
+
+
+def make_descs(bufs, nbytes, counts, widths):
+    """ctypes array of ppc_desc from parallel sequences of device addresses
+    (ints), byte lengths, counter addresses and widths."""
+    n = len(nbytes)
+    arr = (ppc_desc * n)()
+    for i in range(n):
+        arr[i].buf = int(bufs[i]) if bufs[i] is not None else None
+        arr[i].nbytes = int(nbytes[i])
+        arr[i].counts = int(counts[i])
+        arr[i].width = int(widths[i])
+        arr[i].reserved = 0
+    return arr
+
+
+def ppc_plan_create(descs, n=None, opts=None, stream=None):
+    """Returns an opaque plan handle (int).  ``descs`` is a ctypes array of
+    ppc_desc (see make_descs); ``opts`` a ppc_plan_opts or None."""
+    handle = _c_ptr()
+    n = len(descs) if n is None else n
+    rc = lib().ppc_plan_create(ctypes.byref(handle), descs, n,
+                               ctypes.byref(opts) if opts is not None else None, _stream(stream))
+    _check(rc, "ppc_plan_create")
+    return handle.value
+
+
+def ppc_plan_run(plan, stream=None):
+    _check(lib().ppc_plan_run(plan, _stream(stream)), "ppc_plan_run")
+
+
+def ppc_plan_get_info(plan) -> dict:
+    info = ppc_plan_info()
+    _check(lib().ppc_plan_get_info(plan, ctypes.byref(info)), "ppc_plan_get_info")
+    return {k: getattr(info, k) for k, _ in ppc_plan_info._fields_}
+
+
+def ppc_plan_destroy(plan):
+    _check(lib().ppc_plan_destroy(plan), "ppc_plan_destroy")
+
+
+def ppc_server_create(pool, pool_bytes=None, column_bytes=None, cfg=None):
+    """Returns an opaque server handle over a device pool tensor (or address)."""
+    handle = _c_ptr()
+    rc = lib().ppc_server_create(ctypes.byref(handle), _ptr(pool), _nbytes(pool, pool_bytes),
+                                 int(column_bytes), ctypes.byref(cfg) if cfg is not None else None)
+    _check(rc, "ppc_server_create")
+    return handle.value
+
+
+def ppc_server_submit(server, column, width, offset, nbytes, tag=0) -> int:
+    """Returns PPC_OK or PPC_EBUSY; raises on other errors."""
+    req = ppc_request(int(column), int(width), int(offset), int(nbytes), int(tag))
+    rc = lib().ppc_server_submit(server, ctypes.byref(req))
+    if rc not in (PPC_OK, PPC_EBUSY):
+        raise PpcError(rc, "ppc_server_submit")
+    return rc
+
+
+def ppc_server_poll(server, cap=1024) -> list:
+    out = (ppc_result * cap)()
+    n = _c_size(0)
+    _check(lib().ppc_server_poll(server, out, cap, ctypes.byref(n)), "ppc_server_poll")
+    return [out[i] for i in range(n.value)]
+
+
+def ppc_server_get_stats(server) -> dict:
+    st = ppc_server_stats()
+    _check(lib().ppc_server_get_stats(server, ctypes.byref(st)), "ppc_server_get_stats")
+    return {k: getattr(st, k) for k, _ in ppc_server_stats._fields_}
+
+
+def ppc_server_run_trace(server, column, width, offset, nbytes, arrival_ns):
+    """Open-loop trace through the server.  Returns (results ctypes array,
+    stats dict)."""
+    n = len(nbytes)
+    reqs = (ppc_request * n)()
+    for i in range(n):
+        reqs[i].column, reqs[i].width = int(column[i]), int(width[i])
+        reqs[i].offset, reqs[i].nbytes, reqs[i].tag = int(offset[i]), int(nbytes[i]), i
+    arr = (ctypes.c_uint64 * n)(*[int(a) for a in arrival_ns])
+    results = (ppc_result * n)()
+    st = ppc_trace_stats()
+    _check(lib().ppc_server_run_trace(server, reqs, arr, n, results, ctypes.byref(st)),
+           "ppc_server_run_trace")
+    return results, {k: getattr(st, k) for k, _ in ppc_trace_stats._fields_}
+
+
+def ppc_server_destroy(server):
+    _check(lib().ppc_server_destroy(server), "ppc_server_destroy")
 
 
 # ------------------------------------------------------------ convenience

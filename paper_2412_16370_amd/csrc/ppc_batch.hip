@@ -1,0 +1,460 @@
+// ppc_batch.hip -- batched pospopcnt: many arrays of uneven length and mixed
+// width in one persistent launch.
+//
+// The same per-wave tile walk as the plain call (CSA bit planes, cross-lane
+// reduction) runs over a table of work items (array, tile range).  Waves of
+// a persistent grid take items from a global atomic cursor, largest items
+// first, so a few huge arrays and thousands of tiny ones share the device
+// evenly.  The width is applied only when an item's 64 address-position
+// counts are folded into its array's w counters (Section 5: one kernel,
+// the accumulation function picks the width).  Each item's fold ends in at
+// most w 64-bit atomics into that array's counters, so results are exact
+// and independent of the order in which items run.
+//
+// A plan is built once per batch (validation, work split, autotuned tile
+// and grid sizes) and replayed as a captured hipGraph.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cerrno>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <sys/stat.h>
+#include <vector>
+
+#include "ppc.h"
+#include "ppc_batch.hpp"
+#include "ppc_device.hpp"
+#include "ppc_host.hpp"
+
+namespace ppc {
+
+__global__ void reset_cursor_kernel(uint32_t *cursor) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *cursor = 0u;
+}
+
+__global__ void clear_u64_kernel(unsigned long long *p, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+// Fold of a wave's 64 address-position counts (lane L) into w counters
+// relative to the array's pointer, then at most w atomics.  Lanes L and
+// L' feed the same output when they differ only in address-slot bits that
+// the width ignores: those are summed with cross-lane shuffles first.
+__device__ __forceinline__ void fold_and_add(uint32_t acc, uint32_t width, uint32_t m,
+                                             unsigned long long *counts) {
+    const uint32_t lane = __lane_id();
+    const uint32_t s = width >> 3;
+    uint64_t v = acc;
+    if (s <= 4u) v += __shfl_xor(v, 32);
+    if (s <= 2u) v += __shfl_xor(v, 16);
+    if (s == 1u) v += __shfl_xor(v, 8);
+    if (lane < width && v != 0u) atomicAdd(counts + fold_position(lane, width, m), (unsigned long long)v);
+}
+
+template <int WPB>
+__global__ __launch_bounds__(WPB *kWave) void batched_kernel(const ArrayInfo *__restrict__ arrays,
+                                                             const WorkItem *__restrict__ items, uint32_t n_items,
+                                                             uint32_t *cursor) {
+    const uint32_t lane = __lane_id();
+    uint32_t ticket = 0;
+    if (lane == 0) ticket = atomicAdd(cursor, 1u);
+    uint32_t cur = (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
+    while (cur < n_items) {
+        // take the next ticket now; its latency hides behind this item
+        uint32_t next = 0;
+        if (lane == 0) next = atomicAdd(cursor, 1u);
+        const WorkItem it = items[cur];
+        const ArrayInfo ai = arrays[it.array];
+        const bool has_edge = (it.flags & 1u) != 0u;
+        uint4 edge = zero4();
+        if (has_edge) {
+            if (lane < 32) {
+                if (lane < ai.edge0_len) edge = byte_as_chunk((uint64_t)(ai.edge0 + lane), ai.edge0[lane]);
+            } else if (lane - 32 < ai.edge1_len) {
+                edge = byte_as_chunk((uint64_t)(ai.edge1 + (lane - 32)), ai.edge1[lane - 32]);
+            }
+        }
+        const uint32_t acc =
+            wave_count_tiles<true>(ai.body, ai.n_chunks, ai.n_full, it.tile0, it.tile1, 1u, edge, has_edge);
+        fold_and_add(acc, ai.width, ai.m, ai.counts);
+        cur = (uint32_t)__builtin_amdgcn_readfirstlane((int)next);
+    }
+}
+
+bool make_array_info(ArrayInfo &ai, const void *buf, uint64_t nbytes, uint64_t *counts, uint32_t width) {
+    if (!(width == 8 || width == 16 || width == 32 || width == 64)) return false;
+    if (counts == nullptr || ((uintptr_t)counts & 7u) != 0) return false;
+    if (nbytes > 0 && buf == nullptr) return false;
+    std::memset(&ai, 0, sizeof ai);
+    ai.counts = reinterpret_cast<unsigned long long *>(counts);
+    ai.width = width;
+    ai.m = (uint32_t)((uintptr_t)buf % (width / 8u));
+    if (nbytes == 0) return true;
+    const uintptr_t b0 = (uintptr_t)buf, b1 = b0 + nbytes;
+    const uintptr_t f = (b0 + 15u) & ~(uintptr_t)15u, e = b1 & ~(uintptr_t)15u;
+    if (f < e) {
+        const uint64_t n_chunks = (uint64_t)(e - f) / 16u;
+        const uint64_t n_tiles = (n_chunks + kTileChunks - 1) / kTileChunks;
+        if (n_tiles >= (1ull << 32)) return false;  // > 64 TiB in one array
+        ai.body = reinterpret_cast<const uint4 *>(f);
+        ai.n_chunks = n_chunks;
+        ai.n_full = (uint32_t)(n_chunks / kTileChunks);
+        ai.n_tiles = (uint32_t)n_tiles;
+        ai.edge0 = static_cast<const uint8_t *>(buf);
+        ai.edge0_len = (uint32_t)(f - b0);
+        ai.edge1 = reinterpret_cast<const uint8_t *>(e);
+        ai.edge1_len = (uint32_t)(b1 - e);
+    } else {
+        ai.edge0 = static_cast<const uint8_t *>(buf);
+        ai.edge0_len = (uint32_t)nbytes;  // <= 30
+    }
+    return true;
+}
+
+void append_items(std::vector<WorkItem> &items, const ArrayInfo &ai, uint32_t idx, uint32_t tiles_per_item) {
+    const uint32_t p = std::max(1u, std::min(tiles_per_item, kMaxItemTiles));
+    const bool edges = ai.edge0_len + ai.edge1_len > 0;
+    if (ai.n_tiles == 0) {
+        if (edges) items.push_back(WorkItem{idx, 0u, 0u, 1u});
+        return;
+    }
+    for (uint32_t t = 0; t < ai.n_tiles; t += p) {
+        const uint32_t t1 = (uint32_t)std::min<uint64_t>((uint64_t)t + p, ai.n_tiles);
+        items.push_back(WorkItem{idx, t, t1, (t == 0 && edges) ? 1u : 0u});
+    }
+}
+
+void sort_items_lpt(std::vector<WorkItem> &items) {
+    std::stable_sort(items.begin(), items.end(), [](const WorkItem &x, const WorkItem &y) {
+        return (x.tile1 - x.tile0) > (y.tile1 - y.tile0);
+    });
+}
+
+hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, uint32_t n_items,
+                          uint32_t *cursor_dev, uint32_t waves, hipStream_t st) {
+    hipLaunchKernelGGL(reset_cursor_kernel, dim3(1), dim3(64), 0, st, cursor_dev);
+    if (n_items == 0) return hipGetLastError();
+    constexpr int kWpb = 4;
+    const uint32_t w = std::max<uint32_t>(kWpb, std::min<uint32_t>(waves, n_items + kWpb - 1));
+    const uint32_t blocks = (w + kWpb - 1) / kWpb;
+    hipLaunchKernelGGL(batched_kernel<kWpb>, dim3(blocks), dim3(kWpb * kWave), 0, st, arrays_dev, items_dev, n_items,
+                       cursor_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_u64(unsigned long long *p, uint64_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(clear_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+// ---- autotuner cache ------------------------------------------------------
+static std::mutex g_tune_mu;
+
+static std::string tune_cache_path() {
+    if (const char *p = std::getenv("PPC_TUNE_CACHE")) return p;
+    const char *home = std::getenv("HOME");
+    std::string dir = std::string(home && *home ? home : "/tmp") + "/.cache";
+    ::mkdir(dir.c_str(), 0755);
+    return dir + "/ppc_tune.txt";
+}
+
+static int log2_bucket(uint64_t v) {
+    int b = 0;
+    while (v > 1) {
+        v >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+static bool tune_lookup(const std::string &key, uint32_t &p, uint32_t &waves) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = std::fopen(tune_cache_path().c_str(), "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[400];
+        unsigned a = 0, b = 0;
+        if (std::sscanf(line, "%399s %u %u", k, &a, &b) == 3 && key == k && a > 0 && b > 0) {
+            p = a;
+            waves = b;
+            found = true;  // the last matching line wins
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void tune_store(const std::string &key, uint32_t p, uint32_t waves) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = std::fopen(tune_cache_path().c_str(), "a");
+    if (!f) return;
+    std::fprintf(f, "%s %u %u\n", key.c_str(), p, waves);
+    std::fclose(f);
+}
+
+}  // namespace ppc
+
+using namespace ppc;
+
+struct ppc_plan {
+    int device = 0;
+    std::vector<ArrayInfo> arrays;
+    ArrayInfo *arrays_dev = nullptr;
+    WorkItem *items_dev = nullptr;
+    uint32_t *cursor_dev = nullptr;
+    uint32_t n_items = 0;
+    uint32_t tiles_per_item = 0;
+    uint32_t waves = 0;
+    uint64_t total_bytes = 0;
+    uint32_t tuned = 0;  // 0 = given/heuristic, 1 = measured now, 2 = from cache
+    bool use_graph = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void plan_free(ppc_plan *p) {
+    if (!p) return;
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->arrays_dev) (void)hipFree(p->arrays_dev);
+    if (p->items_dev) (void)hipFree(p->items_dev);
+    if (p->cursor_dev) (void)hipFree(p->cursor_dev);
+    delete p;
+}
+
+std::vector<WorkItem> build_items(const std::vector<ArrayInfo> &arrays, uint32_t tiles_per_item) {
+    std::vector<WorkItem> items;
+    items.reserve(arrays.size() * 2);
+    for (uint32_t i = 0; i < (uint32_t)arrays.size(); ++i) append_items(items, arrays[i], i, tiles_per_item);
+    sort_items_lpt(items);
+    return items;
+}
+
+// Times one (tiles_per_item, waves) candidate on the plan's arrays with the
+// counters redirected to scratch; returns the median of `reps` runs in ms.
+ppc_status time_candidate(const ArrayInfo *tune_arrays_dev, const std::vector<ArrayInfo> &arrays, uint32_t p,
+                          uint32_t waves, uint32_t *cursor_dev, hipStream_t st, int reps, float &ms_out) {
+    std::vector<WorkItem> items = build_items(arrays, p);
+    WorkItem *items_dev = nullptr;
+    if (!items.empty() && hipMalloc(&items_dev, items.size() * sizeof(WorkItem)) != hipSuccess) return PPC_ENOMEM;
+    ppc_status rc = PPC_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<float> t;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = PPC_EDEVICE;
+    if (rc == PPC_OK && !items.empty() &&
+        hipMemcpyAsync(items_dev, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        rc = PPC_EDEVICE;
+    for (int r = 0; rc == PPC_OK && r <= reps; ++r) {  // run 0 warms up
+        if (hipEventRecord(e0, st) != hipSuccess ||
+            launch_batched(tune_arrays_dev, items_dev, (uint32_t)items.size(), cursor_dev, waves, st) != hipSuccess ||
+            hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = PPC_EDEVICE;
+            break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (r > 0) t.push_back(ms);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (items_dev) (void)hipFree(items_dev);
+    if (rc == PPC_OK) {
+        std::sort(t.begin(), t.end());
+        ms_out = t[t.size() / 2];
+    }
+    return rc;
+}
+
+ppc_status autotune(ppc_plan *p, hipStream_t st, uint32_t &best_p, uint32_t &best_w) {
+    const int cus = device_cus(p->device);
+    const size_t n = p->arrays.size();
+    // redirect every array's counters into scratch so tuning runs leave the
+    // caller's counters untouched
+    std::vector<ArrayInfo> tune = p->arrays;
+    unsigned long long *scratch = nullptr;
+    ArrayInfo *tune_dev = nullptr;
+    if (hipMalloc(&scratch, n * 64 * sizeof(unsigned long long)) != hipSuccess) return PPC_ENOMEM;
+    for (size_t i = 0; i < n; ++i) tune[i].counts = scratch + i * 64;
+    ppc_status rc = PPC_OK;
+    if (hipMalloc(&tune_dev, n * sizeof(ArrayInfo)) != hipSuccess) rc = PPC_ENOMEM;
+    if (rc == PPC_OK &&
+        hipMemcpyAsync(tune_dev, tune.data(), n * sizeof(ArrayInfo), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = PPC_EDEVICE;
+    const uint32_t cand_p[] = {4, 16, 64, 256};
+    const uint32_t cand_w[] = {4, 8, 16};
+    float best = 1e30f;
+    for (uint32_t cp : cand_p)
+        for (uint32_t cw : cand_w) {
+            if (rc != PPC_OK) break;
+            float ms = 0;
+            rc = time_candidate(tune_dev, tune, cp, cw * (uint32_t)cus, p->cursor_dev, st, 3, ms);
+            if (rc == PPC_OK && ms < best) {
+                best = ms;
+                best_p = cp;
+                best_w = cw * (uint32_t)cus;
+            }
+        }
+    (void)hipStreamSynchronize(st);
+    if (tune_dev) (void)hipFree(tune_dev);
+    (void)hipFree(scratch);
+    return rc;
+}
+
+std::string tune_key(const ppc_plan *p) {
+    std::vector<uint64_t> len;
+    len.reserve(p->arrays.size());
+    uint64_t mx = 0;
+    for (const auto &a : p->arrays) {
+        const uint64_t b = a.n_chunks * 16u + a.edge0_len + a.edge1_len;
+        len.push_back(b);
+        mx = std::max(mx, b);
+    }
+    uint64_t med = 0;
+    if (!len.empty()) {
+        std::nth_element(len.begin(), len.begin() + len.size() / 2, len.end());
+        med = len[len.size() / 2];
+    }
+    hipDeviceProp_t prop;
+    std::string name = "gpu";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) name = prop.gcnArchName;
+    for (auto &ch : name)
+        if (ch == ' ' || ch == ':') ch = '_';
+    char buf[384];
+    std::snprintf(buf, sizeof buf, "batched/%s/cu%d/n%d/bytes%d/med%d/max%d", name.c_str(), device_cus(p->device),
+                  log2_bucket(p->arrays.size()), log2_bucket(p->total_bytes), log2_bucket(med), log2_bucket(mx));
+    return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+ppc_status ppc_plan_create(ppc_plan **out, const ppc_desc *descs, size_t n, const ppc_plan_opts *opts,
+                           void *stream) {
+    if (out == nullptr) return PPC_EINVAL;
+    *out = nullptr;
+    if (n > 0 && descs == nullptr) return PPC_EINVAL;
+    if (n >= (1ull << 31)) return PPC_EINVAL;
+    if (opts && opts->reserved != 0) return PPC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    auto *p = new (std::nothrow) ppc_plan();
+    if (!p) return PPC_ENOMEM;
+    p->arrays.resize(n);
+    for (size_t i = 0; i < n; ++i) {  // all argument checks come before any HIP call
+        if (descs[i].reserved != 0 ||
+            !make_array_info(p->arrays[i], descs[i].buf, descs[i].nbytes, descs[i].counts, descs[i].width)) {
+            plan_free(p);
+            return PPC_EINVAL;
+        }
+        p->total_bytes += descs[i].nbytes;
+    }
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        plan_free(p);
+        return PPC_EDEVICE;
+    }
+    if (hipMalloc(&p->cursor_dev, sizeof(uint32_t)) != hipSuccess) {
+        plan_free(p);
+        return PPC_ENOMEM;
+    }
+    const int cus = device_cus(p->device);
+    uint32_t tp = opts ? opts->tiles_per_item : 0u;
+    uint32_t wv = opts ? opts->waves : 0u;
+    const bool want_tune = opts ? opts->autotune != 0 : true;
+    if (tp == 0 || wv == 0) {
+        uint32_t bp = 16, bw = 8u * (uint32_t)cus;  // heuristic default
+        const std::string key = tune_key(p);
+        if (want_tune && tune_lookup(key, bp, bw)) {
+            p->tuned = 2;
+        } else if (want_tune && n > 0 && p->total_bytes >= ((uint64_t)64 << 20)) {
+            ppc_status rc = autotune(p, st, bp, bw);
+            if (rc != PPC_OK) {
+                plan_free(p);
+                return rc;
+            }
+            tune_store(key, bp, bw);
+            p->tuned = 1;
+        }
+        if (tp == 0) tp = bp;
+        if (wv == 0) wv = bw;
+    }
+    p->tiles_per_item = std::min(tp, kMaxItemTiles);
+    p->waves = wv;
+    std::vector<WorkItem> items = build_items(p->arrays, p->tiles_per_item);
+    p->n_items = (uint32_t)items.size();
+    if ((n > 0 && hipMalloc(&p->arrays_dev, n * sizeof(ArrayInfo)) != hipSuccess) ||
+        (!items.empty() && hipMalloc(&p->items_dev, items.size() * sizeof(WorkItem)) != hipSuccess)) {
+        plan_free(p);
+        return PPC_ENOMEM;
+    }
+    if ((n > 0 && hipMemcpyAsync(p->arrays_dev, p->arrays.data(), n * sizeof(ArrayInfo), hipMemcpyHostToDevice,
+                                 st) != hipSuccess) ||
+        (!items.empty() && hipMemcpyAsync(p->items_dev, items.data(), items.size() * sizeof(WorkItem),
+                                          hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        plan_free(p);
+        return PPC_EDEVICE;
+    }
+    p->use_graph = opts ? opts->use_graph != 0 : true;
+    if (p->use_graph) {
+        hipStream_t cap = nullptr;
+        bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            const bool launched =
+                launch_batched(p->arrays_dev, p->items_dev, p->n_items, p->cursor_dev, p->waves, cap) == hipSuccess;
+            ok = hipStreamEndCapture(cap, &p->graph) == hipSuccess && launched;
+        }
+        ok = ok && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+        if (cap) (void)hipStreamDestroy(cap);
+        if (!ok) {
+            plan_free(p);
+            return PPC_EDEVICE;
+        }
+    }
+    *out = p;
+    return PPC_OK;
+}
+
+ppc_status ppc_plan_run(ppc_plan *p, void *stream) {
+    if (!p) return PPC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->use_graph) return hipGraphLaunch(p->exec, st) == hipSuccess ? PPC_OK : PPC_EDEVICE;
+    return launch_batched(p->arrays_dev, p->items_dev, p->n_items, p->cursor_dev, p->waves, st) == hipSuccess
+               ? PPC_OK
+               : PPC_EDEVICE;
+}
+
+ppc_status ppc_plan_get_info(const ppc_plan *p, ppc_plan_info *info) {
+    if (!p || !info) return PPC_EINVAL;
+    info->n_arrays = p->arrays.size();
+    info->n_items = p->n_items;
+    info->total_bytes = p->total_bytes;
+    info->tiles_per_item = p->tiles_per_item;
+    info->waves = p->waves;
+    info->tuned = p->tuned;
+    info->graph = p->use_graph ? 1u : 0u;
+    return PPC_OK;
+}
+
+ppc_status ppc_plan_destroy(ppc_plan *p) {
+    if (!p) return PPC_EINVAL;
+    (void)hipDeviceSynchronize();
+    plan_free(p);
+    return PPC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,56 @@
+// ppc_batch.hpp -- work-item tables shared by the batched plan and the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "ppc.h"
+
+namespace ppc {
+
+// One array of a batch, as the persistent kernel sees it (64 bytes).
+struct ArrayInfo {
+    const uint4 *body;          // first full 16-byte chunk (nullptr if none)
+    uint64_t n_chunks;          // full chunks
+    const uint8_t *edge0;       // head bytes
+    const uint8_t *edge1;       // tail bytes
+    unsigned long long *counts; // w counters
+    uint32_t n_full;            // whole tiles
+    uint32_t n_tiles;           // whole tiles + partial tile
+    uint32_t edge0_len, edge1_len;
+    uint32_t width, m;          // width and buf mod (w/8)
+};
+static_assert(sizeof(ArrayInfo) == 64, "ArrayInfo layout");
+
+// One unit of work: tiles [tile0, tile1) of array `array`; flag bit 0 = this
+// item also counts the array's head/tail bytes.
+struct WorkItem {
+    uint32_t array;
+    uint32_t tile0, tile1;
+    uint32_t flags;
+};
+static_assert(sizeof(WorkItem) == 16, "WorkItem layout");
+
+// Per-item tile cap: keeps every per-wave 32-bit count below 2^31.
+constexpr uint32_t kMaxItemTiles = 1u << 20;
+
+// Fills `ai` for one array.  Returns false for an invalid array.
+bool make_array_info(ArrayInfo &ai, const void *buf, uint64_t nbytes, uint64_t *counts, uint32_t width);
+
+// Appends the work items of array `idx` (tiles split into pieces of at most
+// `tiles_per_item`).
+void append_items(std::vector<WorkItem> &items, const ArrayInfo &ai, uint32_t idx, uint32_t tiles_per_item);
+
+// Sorts items largest first (longest-processing-time order).
+void sort_items_lpt(std::vector<WorkItem> &items);
+
+// Enqueues the cursor reset and the persistent kernel on `st`.
+hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, uint32_t n_items,
+                          uint32_t *cursor_dev, uint32_t waves, hipStream_t st);
+
+// Enqueues a kernel that clears n uint64 counters (graph-safe, no memset).
+hipError_t launch_clear_u64(unsigned long long *p, uint64_t n, hipStream_t st);
+
+}  // namespace ppc

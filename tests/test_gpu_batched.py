@@ -1,0 +1,208 @@
+"""GPU parity of the batched form (ppc_plan_*) against the oracle and the plain call.
+
+Every array of a batch must get exactly the counts the oracle gives for its
+bytes and width (tolerance 0), and exactly what a plain call adds.  Arrays
+sit in one pool filled with 0xFF between them, so a read outside any array
+changes some count.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def ppc():
+    import paper_2412_16370_amd as ppc
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ppc.lib()
+    return ppc
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def make_pool(spec, seed):
+    """Device pool with array i at spec offsets[i], Bernoulli(p_i) bits, 0xFF
+    between arrays."""
+    pool = torch.full((spec["pool_bytes"] + 128,), 0xFF, dtype=torch.uint8, device=dev())
+    for i, (off, n, p) in enumerate(zip(spec["offsets"], spec["lengths"], spec["p"])):
+        if n:
+            synth.device_bernoulli(int(n), float(p), seed=seed * 1_000_003 + i, device=dev(),
+                                   out=pool[int(off):int(off) + int(n)])
+    torch.cuda.synchronize()
+    return pool
+
+
+def plan_for(ppc, pool, spec, counts, opts=None):
+    n = len(spec["lengths"])
+    base, cbase = pool.data_ptr(), counts.data_ptr()
+    descs = ppc.make_descs([base + int(o) for o in spec["offsets"]], spec["lengths"],
+                           [cbase + i * 64 * 8 for i in range(n)], spec["widths"])
+    return ppc.ppc_plan_create(descs, n, opts)
+
+
+def plain_counts(ppc, pool, spec):
+    n = len(spec["lengths"])
+    counts = torch.zeros((n, 64), dtype=torch.int64, device=dev())
+    lib = ppc.lib()
+    st = torch.cuda.current_stream().cuda_stream
+    base, cbase = pool.data_ptr(), counts.data_ptr()
+    for i in range(n):
+        rc = lib.ppc_pospopcnt(int(spec["widths"][i]), cbase + i * 512, base + int(spec["offsets"][i]),
+                               int(spec["lengths"][i]), st)
+        assert rc == 0
+    torch.cuda.synchronize()
+    return ppc.counts_to_numpy(counts)
+
+
+def oracle_rows(host_pool, spec, idx):
+    rows = {}
+    for i in idx:
+        o, n, w = int(spec["offsets"][i]), int(spec["lengths"][i]), int(spec["widths"][i])
+        rows[i] = oracle.pospopcnt(host_pool[o:o + n], w)
+    return rows
+
+
+def check_rows(got, spec, want_rows, reps=1):
+    for i, want in want_rows.items():
+        w = int(spec["widths"][i])
+        assert np.array_equal(got[i, :w], want * np.uint64(reps)), "array %d (w=%d, n=%d)" % (
+            i, w, int(spec["lengths"][i]))
+        assert not got[i, w:].any(), "array %d wrote past its %d counters" % (i, w)
+
+
+def opts(ppc, tiles=0, waves=0, autotune=0, graph=1):
+    return ppc.ppc_plan_opts(tiles, waves, autotune, graph, 0)
+
+
+def test_mixed_batch_unaligned_starts(ppc):
+    spec = synth.batch_spec(3000, seed=30, lo=16, hi=1 * MiB, start_jitter=64)
+    pool = make_pool(spec, seed=30)
+    counts = torch.zeros((3000, 64), dtype=torch.int64, device=dev())
+    plan = plan_for(ppc, pool, spec, counts, opts(ppc, tiles=4))
+    try:
+        ppc.ppc_plan_run(plan)
+        torch.cuda.synchronize()
+        info = ppc.ppc_plan_get_info(plan)
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    assert info["n_arrays"] == 3000 and info["tiles_per_item"] == 4 and info["graph"] == 1
+    assert info["n_items"] > 3000  # large arrays were split
+    got = ppc.counts_to_numpy(counts).reshape(3000, 64)
+    check_rows(got, spec, oracle_rows(pool.cpu().numpy(), spec, range(3000)))
+    assert np.array_equal(got, plain_counts(ppc, pool, spec))
+
+
+def test_edge_only_and_empty_arrays(ppc):
+    # every length 0..40 at every start offset 0..15, all widths
+    offs, lens, widths = [], [], []
+    pos = 0
+    for w in (8, 16, 32, 64):
+        for o in range(16):
+            for n in range(41):
+                offs.append(pos + o)
+                lens.append(n)
+                widths.append(w)
+                pos += 128
+    spec = dict(offsets=np.array(offs), lengths=np.array(lens), widths=np.array(widths),
+                p=np.full(len(lens), 0.5), pool_bytes=pos + 128)
+    pool = make_pool(spec, seed=31)
+    n = len(lens)
+    counts = torch.zeros((n, 64), dtype=torch.int64, device=dev())
+    plan = plan_for(ppc, pool, spec, counts, opts(ppc, graph=0))
+    try:
+        ppc.ppc_plan_run(plan)
+        torch.cuda.synchronize()
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    got = ppc.counts_to_numpy(counts).reshape(n, 64)
+    check_rows(got, spec, oracle_rows(pool.cpu().numpy(), spec, range(n)))
+
+
+def test_autotuned_plan_replays_and_cache(ppc, tmp_path, monkeypatch):
+    monkeypatch.setenv("PPC_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    spec = synth.batch_spec(800, seed=32, lo=16, hi=4 * MiB)
+    assert spec["pool_bytes"] > 64 * MiB  # large enough to be tuned
+    pool = make_pool(spec, seed=32)
+    counts = torch.zeros((800, 64), dtype=torch.int64, device=dev())
+    plan = plan_for(ppc, pool, spec, counts)  # default options: autotune + graph
+    try:
+        info = ppc.ppc_plan_get_info(plan)
+        assert info["tuned"] == 1 and info["graph"] == 1
+        # graph replays with eager work and synchronisations in between
+        scratch = torch.zeros(1 << 20, device=dev())
+        for r in range(3):
+            ppc.ppc_plan_run(plan)
+            scratch.add_(1.0)
+            torch.cuda.synchronize()
+            got = ppc.counts_to_numpy(counts).reshape(800, 64)
+            if r == 0:
+                want = oracle_rows(pool.cpu().numpy(), spec, range(800))
+            check_rows(got, spec, want, reps=r + 1)
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    counts2 = torch.zeros((800, 64), dtype=torch.int64, device=dev())
+    plan2 = plan_for(ppc, pool, spec, counts2)
+    try:
+        info2 = ppc.ppc_plan_get_info(plan2)
+        assert info2["tuned"] == 2
+        assert (info2["tiles_per_item"], info2["waves"]) == (info["tiles_per_item"], info["waves"])
+    finally:
+        ppc.ppc_plan_destroy(plan2)
+    assert not counts2.any()  # tuning never touched the caller's counters
+
+
+def test_ten_thousand_arrays_full_size(ppc, tmp_path, monkeypatch):
+    """10,000 arrays, log-uniform 16 B .. 16 MiB, mixed widths, p ~ U[0,1]:
+    batched == plain for every array; == oracle for every array up to 1 MiB
+    and a seeded 1% sample of the larger ones."""
+    monkeypatch.setenv("PPC_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    spec = synth.batch_spec(10_000, seed=3)
+    pool = make_pool(spec, seed=3)
+    counts = torch.zeros((10_000, 64), dtype=torch.int64, device=dev())
+    plan = plan_for(ppc, pool, spec, counts)
+    try:
+        ppc.ppc_plan_run(plan)
+        torch.cuda.synchronize()
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    got = ppc.counts_to_numpy(counts).reshape(10_000, 64)
+    assert np.array_equal(got, plain_counts(ppc, pool, spec))
+    small = [i for i in range(10_000) if spec["lengths"][i] <= MiB]
+    big = [i for i in range(10_000) if spec["lengths"][i] > MiB]
+    sample = sorted(np.random.default_rng(99).choice(big, size=max(1, len(big) // 100), replace=False))
+    want = {}
+    for i in small + list(sample):
+        o, n, w = int(spec["offsets"][i]), int(spec["lengths"][i]), int(spec["widths"][i])
+        want[i] = oracle.pospopcnt(pool[o:o + n].cpu().numpy(), w)
+    check_rows(got, spec, want)
+
+
+def test_empty_plan_and_bad_descriptors(ppc):
+    plan = ppc.ppc_plan_create(ppc.make_descs([], [], [], []), 0, None)
+    ppc.ppc_plan_run(plan)
+    torch.cuda.synchronize()
+    assert ppc.ppc_plan_get_info(plan)["n_items"] == 0
+    ppc.ppc_plan_destroy(plan)
+    buf = torch.zeros(64, dtype=torch.uint8, device=dev())
+    counts = torch.zeros(64, dtype=torch.int64, device=dev())
+    for bad in ([buf.data_ptr()], [64], [counts.data_ptr() + 4], [16]), \
+               ([buf.data_ptr()], [64], [counts.data_ptr()], [7]), \
+               ([None], [64], [counts.data_ptr()], [8]):
+        with pytest.raises(ppc.PpcError) as e:
+            ppc.ppc_plan_create(ppc.make_descs(*bad), 1, None)
+        assert e.value.status == ppc.PPC_EINVAL
+    torch.cuda.synchronize()
+    assert not counts.any()
