@@ -100,6 +100,109 @@ def cpu_baseline(seconds_target=15.0):
             "single_thread_GBps": round(st, 4)}
 
 
+def batched_leg(ppc, torch, synth, dev, reps):
+    """10,000 arrays, log-uniform 16 B .. 16 MiB, mixed widths, per-array
+    density p ~ U[0,1]: one graph launch of the persistent batched kernel
+    against 10,000 plain calls on one stream (same GPU, same bytes)."""
+    spec = synth.batch_spec(10_000, seed=3)
+    n = len(spec["lengths"])
+    pool = torch.full((spec["pool_bytes"] + 128,), 0xFF, dtype=torch.uint8, device=dev)
+    for i, (off, ln, p) in enumerate(zip(spec["offsets"], spec["lengths"], spec["p"])):
+        synth.device_bernoulli(int(ln), float(p), seed=3 * 1_000_003 + i, device=dev,
+                               out=pool[int(off):int(off) + int(ln)])
+    counts = torch.zeros((n, 64), dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    total = int(spec["lengths"].sum())
+    base, cbase = pool.data_ptr(), counts.data_ptr()
+    addrs = [base + int(o) for o in spec["offsets"]]
+    caddr = [cbase + i * 512 for i in range(n)]
+    t0 = time.perf_counter()
+    plan = ppc.ppc_plan_create(ppc.make_descs(addrs, spec["lengths"], caddr, spec["widths"]), n, None)
+    create_s = time.perf_counter() - t0
+    info = ppc.ppc_plan_get_info(plan)
+    stream = torch.cuda.current_stream()
+    ppc.ppc_plan_run(plan)
+    torch.cuda.synchronize()
+    ms = time_calls(lambda b, i: ppc.ppc_plan_run(plan), [None], reps, torch)
+    ppc.ppc_plan_destroy(plan)
+    batched_ms = sorted(ms)[len(ms) // 2]
+    # the same arrays as 10,000 plain calls back to back on one stream
+    lib = ppc.lib()
+    widths = [int(w) for w in spec["widths"]]
+    lens = [int(x) for x in spec["lengths"]]
+    st = stream.cuda_stream
+    plain_ms = []
+    for r in range(max(2, reps // 4)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for i in range(n):
+            lib.ppc_pospopcnt(widths[i], caddr[i], addrs[i], lens[i], st)
+        b.record(stream)
+        torch.cuda.synchronize()
+        plain_ms.append(a.elapsed_time(b))
+    plain_med = sorted(plain_ms)[len(plain_ms) // 2]
+    del pool, counts
+    torch.cuda.empty_cache()
+    return {"n_arrays": n, "total_bytes": total,
+            "batched_GBps": round(total / (batched_ms * 1e-3) / 1e9, 1),
+            "batched_ms": round(batched_ms, 3),
+            "plain_calls_GBps": round(total / (plain_med * 1e-3) / 1e9, 1),
+            "plain_calls_ms": round(plain_med, 3),
+            "speedup_vs_plain": round(plain_med / batched_ms, 3),
+            "tiles_per_item": info["tiles_per_item"], "waves": info["waves"],
+            "n_items": info["n_items"], "tuned": ["given", "measured", "cache"][info["tuned"]],
+            "plan_create_s": round(create_s, 3)}
+
+
+def served_leg(ppc, torch, synth, dev, plain_gbps, n_requests=100_000, rho=0.5):
+    """1 GiB pool of one-hot uint32 columns (16 x 64 MiB, 32 categories, Zipf
+    s = 1.0); Poisson requests (column, width, offset, length log-uniform
+    64 B .. 64 MiB) offered at rho x the plain kernel's bandwidth."""
+    col_bytes = 64 * MiB
+    pool = synth.device_onehot_u32_columns(16, col_bytes // 4, seed=4, device=dev)
+    torch.cuda.synchronize()
+    mean_len = synth.log_uniform_mean(64, 64 * MiB)
+    rate = rho * plain_gbps * 1e9 / mean_len
+    t = synth.serve_trace(n_requests, seed=4, n_columns=16, column_bytes=col_bytes, rate_per_s=rate,
+                          lo=64, hi=64 * MiB)
+    out = {"n_requests": n_requests, "offered_load": rho, "offered_req_per_s": round(rate),
+           "offered_GBps": round(rho * plain_gbps, 1)}
+    for name, cfg in (("continuous", None),
+                      ("one_at_a_time", ppc.ppc_server_cfg(1, 1, 0, 0, 0, 0, 0))):
+        server = ppc.ppc_server_create(pool, column_bytes=col_bytes, cfg=cfg)
+        try:
+            k = n_requests if name == "continuous" else min(n_requests, 20_000)
+            _, st = ppc.ppc_server_run_trace(server, t["column"][:k], t["width"][:k], t["offset"][:k],
+                                             t["length"][:k], t["arrival_ns"][:k])
+        finally:
+            ppc.ppc_server_destroy(server)
+        out[name] = {"requests": k, "p50_us": round(st["p50_ns"] / 1e3, 1),
+                     "p99_us": round(st["p99_ns"] / 1e3, 1), "mean_us": round(st["mean_ns"] / 1e3, 1),
+                     "max_us": round(st["max_ns"] / 1e3, 1), "GBps": round(st["gbps"], 1),
+                     "batches": st["batches"], "mean_batch": round(st["mean_batch"], 2),
+                     "busy_rejections": st["busy_rejections"]}
+        log("served %s: p50 %.1f us p99 %.1f us, %.1f GB/s, mean batch %.1f" % (
+            name, st["p50_ns"] / 1e3, st["p99_ns"] / 1e3, st["gbps"], st["mean_batch"]))
+    # plain calls for the first 20,000 requests, back to back (closed loop)
+    lib = ppc.lib()
+    k = min(n_requests, 20_000)
+    counts = torch.zeros((k, 64), dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    base, cb, st = pool.data_ptr(), counts.data_ptr(), stream.cuda_stream
+    a.record(stream)
+    for i in range(k):
+        lib.ppc_pospopcnt(int(t["width"][i]), cb + i * 512,
+                          base + int(t["column"][i]) * col_bytes + int(t["offset"][i]),
+                          int(t["length"][i]), st)
+    b.record(stream)
+    torch.cuda.synchronize()
+    out["plain_back_to_back_GBps"] = round(int(t["length"][:k].sum()) / (a.elapsed_time(b) * 1e-3) / 1e9, 1)
+    del pool, counts
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +327,14 @@ def main():
     }
     del bufs
     torch.cuda.empty_cache()
+
+    if not args.no_batched:
+        log("batched leg: 10,000 arrays")
+        result["batched"] = batched_leg(ppc, torch, synth, dev, reps=max(8, args.steps))
+        log("batched: %s" % result["batched"])
+    if not args.no_served:
+        log("served leg: Poisson trace at half of the plain bandwidth")
+        result["served"] = served_leg(ppc, torch, synth, dev, achieved)
 
     if not args.no_cpu:
         log("timing the CPU oracle baseline")

@@ -153,3 +153,25 @@ def device_bernoulli(n: int, p: float, seed: int, device="cuda", out=None):
         bits = torch.rand((hi - lo, 8), generator=g, device=device) < p
         out[lo:hi] = (bits.to(torch.uint8) * weights).sum(dim=1, dtype=torch.uint8)
     return out
+
+
+def device_onehot_u32_columns(n_columns: int, words_per_column: int, seed: int, device="cuda",
+                              n_cat: int = 32, s: float = 1.0):
+    """Device-generated serving pool (same law as onehot_u32_columns, drawn
+    with torch's seeded generator by inverse-CDF lookup).  Returns the pool
+    as a uint8 device tensor."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    cdf = torch.tensor(np.cumsum(zipf_probs(n_cat, s)), dtype=torch.float64, device=device)
+    cdf[-1] = 1.0
+    n = n_columns * words_per_column
+    out = torch.empty(n, dtype=torch.int32, device=device)
+    chunk = 1 << 24
+    for lo in range(0, n, chunk):
+        hi = min(n, lo + chunk)
+        u = torch.rand(hi - lo, generator=g, device=device, dtype=torch.float64)
+        cat = torch.searchsorted(cdf, u, right=True).clamp_(max=n_cat - 1)
+        out[lo:hi] = torch.bitwise_left_shift(torch.ones_like(cat), cat).to(torch.int32)
+    return out.view(torch.uint8)
