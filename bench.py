@@ -37,11 +37,19 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the code (comments and blank lines stripped) of the sources
+    the plain pospopcnt kernel is built from."""
+    import re
+
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2412_16370_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+    for name in ("ppc_device.hpp", "ppc_plain.hip"):
+        with open(os.path.join(csrc, name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        code = "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
+        h.update(name.encode() + b"\0" + code.encode())
     return h.hexdigest()[:16]
 
 

@@ -12,7 +12,7 @@
  *     never cleared (Section 4, step 1 and its footnote).
  *   - Word i is the little-endian integer of bytes buf[i*s .. i*s+s-1] with
  *     s = w/8 (all machines the paper targets are little-endian; heads and
- *     tails are masked bytewise, Sections 4.1 and 4.5).
+ *     tails are masked bytewise, Sections 4.1 and 4.6).
  *   - A trailing partial word is read with its missing high bytes as zero,
  *     so every byte of [buf, buf+nbytes) is counted exactly once.
  *   - Bit positions are relative to the caller's pointer, not to absolute

@@ -126,7 +126,7 @@ __device__ __forceinline__ uint32_t wave_in_block() {
 }
 
 // One stage of a 32x32 bit-matrix transpose across the lanes of each 32-lane
-// half (the recursive block transpose of Section 4.4, done across lanes
+// half (the recursive block transpose of Section 4.5, done across lanes
 // instead of inside one register).  Row = lane, column = bit.  The rows with
 // (row & S) == 0 trade their columns with (col & S) != 0 for the partner's
 // columns with (col & S) == 0.
@@ -166,7 +166,7 @@ __device__ __forceinline__ uint32_t column_popcount(uint32_t x, const TransposeC
 }
 
 // End-of-segment reduction of a wave's bit planes into 64 integer counts
-// (the final accumulation of Section 4.4, rebuilt for a 64-lane wavefront).
+// (the final accumulation of Section 4.5, rebuilt for a 64-lane wavefront).
 // Returns, in lane L, the number of set bits at address position L summed
 // over all lanes and planes with their weights.  All 64 lanes must be
 // active.  Plane e has weight 2^e; planes e >= e_used are zero (e_used is

@@ -5,16 +5,16 @@
 //   head/tail  : bytes before the first and after the last 16-byte aligned
 //                chunk are loaded one per lane by wave 0 and entered as
 //                single-byte chunks (head processing, Section 4.1; tail,
-//                Section 4.5).  Nothing outside [buf, buf+nbytes) is read.
+//                Section 4.6).  Nothing outside [buf, buf+nbytes) is read.
 //   main loop  : each wave walks tiles of 64 lanes x 16 chunks (16 KiB); per
 //                tile every lane runs the CSA_{16+4} network (Section 4.2)
 //                and adds the weight-16 plane to a bit-sliced counter
 //                (the role of the intermediate accumulation, Section 4.3).
 //   overflow   : a segment holds at most 63 tiles so the 6-plane bit-sliced
-//                counter cannot overflow (Section 4.3's flush rule, with the
+//                counter cannot overflow (Section 4.4's flush rule, with the
 //                bound fixed at compile time instead of tracked at run time).
 //   final acc. : planes -> 64 integer counts per wave by cross-lane
-//                transposes and popcounts (Section 4.4).
+//                transposes and popcounts (Section 4.5).
 //   f_w        : per-block LDS partials are folded to w positions relative
 //                to `buf` and added to `counts` with 64-bit atomics.
 #include <hip/hip_runtime.h>
