@@ -188,7 +188,10 @@ def served_leg(ppc, torch, synth, dev, plain_gbps, n_requests=100_000, rho=0.5):
                      "p99_us": round(st["p99_ns"] / 1e3, 1), "mean_us": round(st["mean_ns"] / 1e3, 1),
                      "max_us": round(st["max_ns"] / 1e3, 1), "GBps": round(st["gbps"], 1),
                      "batches": st["batches"], "mean_batch": round(st["mean_batch"], 2),
-                     "busy_rejections": st["busy_rejections"]}
+                     "busy_rejections": st["busy_rejections"],
+                     "host_dispatch_ms": round(st["host_dispatch_ns"] / 1e6, 2),
+                     "host_retire_ms": round(st["host_retire_ns"] / 1e6, 2),
+                     "makespan_ms": round(st["makespan_ns"] / 1e6, 2)}
         log("served %s: p50 %.1f us p99 %.1f us, %.1f GB/s, mean batch %.1f" % (
             name, st["p50_ns"] / 1e3, st["p99_ns"] / 1e3, st["gbps"], st["mean_batch"]))
     # plain calls for the first 20,000 requests, back to back (closed loop)

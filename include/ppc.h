@@ -189,12 +189,14 @@ typedef struct ppc_result {
 typedef struct ppc_server_stats {
     uint64_t inflight, pending, inflight_bytes;
     uint64_t batches, batched_requests, max_batch_seen;
+    uint64_t host_dispatch_ns, host_retire_ns; /* host time enqueuing / retiring */
 } ppc_server_stats;
 
 typedef struct ppc_trace_stats {
     uint64_t n_requests, total_bytes, makespan_ns;
     uint64_t p50_ns, p99_ns, max_ns, mean_ns; /* arrival -> counts on host */
     uint64_t batches, busy_rejections;
+    uint64_t host_dispatch_ns, host_retire_ns; /* host time enqueuing / retiring */
     double mean_batch;
     double gbps; /* total_bytes / makespan, 1 GB = 1e9 B */
 } ppc_trace_stats;

@@ -68,13 +68,15 @@ class ppc_result(ctypes.Structure):
 
 class ppc_server_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("inflight", "pending", "inflight_bytes", "batches",
-                                                "batched_requests", "max_batch_seen")]
+                                                "batched_requests", "max_batch_seen",
+                                                "host_dispatch_ns", "host_retire_ns")]
 
 
 class ppc_trace_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint64) for k in ("n_requests", "total_bytes", "makespan_ns", "p50_ns",
                                                 "p99_ns", "max_ns", "mean_ns", "batches",
-                                                "busy_rejections")] + \
+                                                "busy_rejections", "host_dispatch_ns",
+                                                "host_retire_ns")] + \
                [("mean_batch", ctypes.c_double), ("gbps", ctypes.c_double)]
 
 

@@ -34,13 +34,14 @@
 
 namespace ppc {
 
-__global__ void reset_cursor_kernel(uint32_t *cursor) {
+// Runs before every persistent launch: resets the work cursor and, for the
+// server, clears the batch's counters (a kernel, not a memset, so the whole
+// sequence can live in a hipGraph).
+__global__ void prologue_kernel(uint32_t *cursor, unsigned long long *clear, uint64_t n_clear) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *cursor = 0u;
-}
-
-__global__ void clear_u64_kernel(unsigned long long *p, uint64_t n) {
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-        p[i] = 0ull;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_clear;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        clear[i] = 0ull;
 }
 
 // Fold of a wave's 64 address-position counts (lane L) into w counters
@@ -138,21 +139,16 @@ void sort_items_lpt(std::vector<WorkItem> &items) {
 }
 
 hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, uint32_t n_items,
-                          uint32_t *cursor_dev, uint32_t waves, hipStream_t st) {
-    hipLaunchKernelGGL(reset_cursor_kernel, dim3(1), dim3(64), 0, st, cursor_dev);
+                          uint32_t *cursor_dev, uint32_t waves, hipStream_t st, unsigned long long *clear,
+                          uint64_t n_clear) {
+    const uint64_t pblocks = std::max<uint64_t>(1, std::min<uint64_t>((n_clear + 255) / 256, 256));
+    hipLaunchKernelGGL(prologue_kernel, dim3((unsigned)pblocks), dim3(256), 0, st, cursor_dev, clear, n_clear);
     if (n_items == 0) return hipGetLastError();
     constexpr int kWpb = 4;
     const uint32_t w = std::max<uint32_t>(kWpb, std::min<uint32_t>(waves, n_items + kWpb - 1));
     const uint32_t blocks = (w + kWpb - 1) / kWpb;
     hipLaunchKernelGGL(batched_kernel<kWpb>, dim3(blocks), dim3(kWpb * kWave), 0, st, arrays_dev, items_dev, n_items,
                        cursor_dev);
-    return hipGetLastError();
-}
-
-hipError_t launch_clear_u64(unsigned long long *p, uint64_t n, hipStream_t st) {
-    if (n == 0) return hipSuccess;
-    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 1024);
-    hipLaunchKernelGGL(clear_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

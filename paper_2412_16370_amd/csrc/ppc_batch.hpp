@@ -46,11 +46,10 @@ void append_items(std::vector<WorkItem> &items, const ArrayInfo &ai, uint32_t id
 // Sorts items largest first (longest-processing-time order).
 void sort_items_lpt(std::vector<WorkItem> &items);
 
-// Enqueues the cursor reset and the persistent kernel on `st`.
+// Enqueues the prologue (cursor reset, and a clear of n_clear counters at
+// `clear` if given) and the persistent kernel on `st`.
 hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, uint32_t n_items,
-                          uint32_t *cursor_dev, uint32_t waves, hipStream_t st);
-
-// Enqueues a kernel that clears n uint64 counters (graph-safe, no memset).
-hipError_t launch_clear_u64(unsigned long long *p, uint64_t n, hipStream_t st);
+                          uint32_t *cursor_dev, uint32_t waves, hipStream_t st,
+                          unsigned long long *clear = nullptr, uint64_t n_clear = 0);
 
 }  // namespace ppc

@@ -51,8 +51,9 @@ struct Lane {
     bool busy = false;
     bool failed = false;  // an enqueue of the batch in flight failed
     std::vector<uint32_t> slots;  // slot ids of the batch in flight
-    ArrayInfo *arrays_host = nullptr, *arrays_dev = nullptr;
-    WorkItem *items_host = nullptr, *items_dev = nullptr;
+    // one staging buffer per lane: n ArrayInfo then m WorkItem, copied to
+    // the device in one transfer
+    uint8_t *tables_host = nullptr, *tables_dev = nullptr;
     unsigned long long *counts_dev = nullptr;
     uint64_t *counts_host = nullptr;
     uint32_t *cursor_dev = nullptr;
@@ -76,6 +77,7 @@ struct ppc_server {
     uint64_t inflight_bytes = 0;
     uint32_t inflight = 0;
     uint64_t batches = 0, batched_requests = 0, max_batch_seen = 0;
+    uint64_t host_dispatch_ns = 0, host_retire_ns = 0;  // host time spent enqueuing / retiring
     ppc_status sticky = PPC_OK;  // first device error
 };
 
@@ -87,11 +89,9 @@ void server_free(ppc_server *s) {
         if (l.stream) (void)hipStreamSynchronize(l.stream);
         if (l.done) (void)hipEventDestroy(l.done);
         if (l.stream) (void)hipStreamDestroy(l.stream);
-        if (l.arrays_host) (void)hipHostFree(l.arrays_host);
-        if (l.items_host) (void)hipHostFree(l.items_host);
+        if (l.tables_host) (void)hipHostFree(l.tables_host);
         if (l.counts_host) (void)hipHostFree(l.counts_host);
-        if (l.arrays_dev) (void)hipFree(l.arrays_dev);
-        if (l.items_dev) (void)hipFree(l.items_dev);
+        if (l.tables_dev) (void)hipFree(l.tables_dev);
         if (l.counts_dev) (void)hipFree(l.counts_dev);
         if (l.cursor_dev) (void)hipFree(l.cursor_dev);
     }
@@ -101,6 +101,7 @@ void server_free(ppc_server *s) {
 // Retires finished batches: results move to the completed queue, slots and
 // in-flight bytes are released.
 void retire(ppc_server *s) {
+    const uint64_t t_begin = now_ns();
     for (auto &l : s->lanes) {
         if (!l.busy) continue;
         hipError_t q = hipEventQuery(l.done);
@@ -112,13 +113,13 @@ void retire(ppc_server *s) {
             const uint32_t id = l.slots[i];
             Slot &sl = s->slots[id];
             ppc_result r;
-            std::memset(&r, 0, sizeof r);
             r.tag = sl.req.tag;
             r.width = sl.req.width;
             r.status = q == hipSuccess ? PPC_OK : PPC_EDEVICE;
             r.t_submit_ns = sl.t_submit;
             r.t_done_ns = t;
             std::memcpy(r.counts, l.counts_host + i * 64, sl.req.width * sizeof(uint64_t));
+            std::memset(r.counts + sl.req.width, 0, (64 - sl.req.width) * sizeof(uint64_t));
             s->completed.push_back(r);
             s->inflight_bytes -= sl.req.nbytes;
             s->inflight -= 1;
@@ -128,6 +129,7 @@ void retire(ppc_server *s) {
         l.busy = false;
         l.failed = false;
     }
+    s->host_retire_ns += now_ns() - t_begin;
 }
 
 uint32_t items_needed(const ArrayInfo &ai, uint32_t p) {
@@ -137,11 +139,14 @@ uint32_t items_needed(const ArrayInfo &ai, uint32_t p) {
 
 // Launches pending requests on idle lanes.
 void dispatch(ppc_server *s) {
+    const uint64_t t_begin = now_ns();
+    std::vector<WorkItem> items;
     for (auto &l : s->lanes) {
-        if (s->pending.empty()) return;
+        if (s->pending.empty()) break;
         if (l.busy) continue;
         uint32_t n = 0, n_items = 0;
-        std::vector<WorkItem> items;
+        items.clear();
+        ArrayInfo *arrays = reinterpret_cast<ArrayInfo *>(l.tables_host);
         while (!s->pending.empty() && n < s->cfg.max_batch) {
             const uint32_t id = s->pending.front();
             const ppc_request &rq = s->slots[id].req;
@@ -153,7 +158,7 @@ void dispatch(ppc_server *s) {
             while (items_needed(ai, p) > s->item_cap / 4) p *= 2;
             const uint32_t need = items_needed(ai, p);
             if (n > 0 && n_items + need > s->item_cap) break;
-            l.arrays_host[n] = ai;
+            arrays[n] = ai;
             append_items(items, ai, n, p);
             n_items += need;
             l.slots.push_back(id);
@@ -161,16 +166,15 @@ void dispatch(ppc_server *s) {
             ++n;
         }
         sort_items_lpt(items);
-        std::memcpy(l.items_host, items.data(), items.size() * sizeof(WorkItem));
-        hipError_t e = hipMemcpyAsync(l.arrays_dev, l.arrays_host, n * sizeof(ArrayInfo), hipMemcpyHostToDevice,
-                                      l.stream);
-        if (e == hipSuccess && !items.empty())
-            e = hipMemcpyAsync(l.items_dev, l.items_host, items.size() * sizeof(WorkItem), hipMemcpyHostToDevice,
-                               l.stream);
-        if (e == hipSuccess) e = launch_clear_u64(l.counts_dev, (uint64_t)n * 64, l.stream);
+        const size_t arrays_bytes = (size_t)n * sizeof(ArrayInfo);
+        std::memcpy(l.tables_host + arrays_bytes, items.data(), items.size() * sizeof(WorkItem));
+        const ArrayInfo *arrays_dev = reinterpret_cast<const ArrayInfo *>(l.tables_dev);
+        const WorkItem *items_dev = reinterpret_cast<const WorkItem *>(l.tables_dev + arrays_bytes);
+        hipError_t e = hipMemcpyAsync(l.tables_dev, l.tables_host, arrays_bytes + items.size() * sizeof(WorkItem),
+                                      hipMemcpyHostToDevice, l.stream);
         if (e == hipSuccess)
-            e = launch_batched(l.arrays_dev, l.items_dev, (uint32_t)items.size(), l.cursor_dev, s->cfg.waves,
-                               l.stream);
+            e = launch_batched(arrays_dev, items_dev, (uint32_t)items.size(), l.cursor_dev, s->cfg.waves, l.stream,
+                               l.counts_dev, (uint64_t)n * 64);
         if (e == hipSuccess)
             e = hipMemcpyAsync(l.counts_host, l.counts_dev, (size_t)n * 64 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                                l.stream);
@@ -184,6 +188,7 @@ void dispatch(ppc_server *s) {
         s->batched_requests += n;
         s->max_batch_seen = std::max<uint64_t>(s->max_batch_seen, n);
     }
+    s->host_dispatch_ns += now_ns() - t_begin;
 }
 
 void progress(ppc_server *s) {
@@ -251,15 +256,14 @@ ppc_status ppc_server_create(ppc_server **out, const void *pool, uint64_t pool_b
     s->free_slots.reserve(c.max_inflight);
     for (uint32_t i = c.max_inflight; i-- > 0;) s->free_slots.push_back(i);
     s->lanes.resize(c.n_streams);
+    const size_t tables_bytes = (size_t)c.max_batch * sizeof(ArrayInfo) + (size_t)s->item_cap * sizeof(WorkItem);
     for (auto &l : s->lanes) {
         bool ok = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&l.done, hipEventDisableTiming) == hipSuccess &&
-                  hipHostMalloc((void **)&l.arrays_host, c.max_batch * sizeof(ArrayInfo), 0) == hipSuccess &&
-                  hipHostMalloc((void **)&l.items_host, s->item_cap * sizeof(WorkItem), 0) == hipSuccess &&
+                  hipHostMalloc((void **)&l.tables_host, tables_bytes, 0) == hipSuccess &&
                   hipHostMalloc((void **)&l.counts_host, (size_t)c.max_batch * 64 * sizeof(uint64_t), 0) ==
                       hipSuccess &&
-                  hipMalloc(&l.arrays_dev, c.max_batch * sizeof(ArrayInfo)) == hipSuccess &&
-                  hipMalloc(&l.items_dev, s->item_cap * sizeof(WorkItem)) == hipSuccess &&
+                  hipMalloc(&l.tables_dev, tables_bytes) == hipSuccess &&
                   hipMalloc(&l.counts_dev, (size_t)c.max_batch * 64 * sizeof(uint64_t)) == hipSuccess &&
                   hipMalloc(&l.cursor_dev, sizeof(uint32_t)) == hipSuccess;
         if (!ok) {
@@ -301,6 +305,8 @@ ppc_status ppc_server_get_stats(const ppc_server *s, ppc_server_stats *st) {
     st->batches = s->batches;
     st->batched_requests = s->batched_requests;
     st->max_batch_seen = s->max_batch_seen;
+    st->host_dispatch_ns = s->host_dispatch_ns;
+    st->host_retire_ns = s->host_retire_ns;
     return PPC_OK;
 }
 
@@ -313,6 +319,7 @@ ppc_status ppc_server_run_trace(ppc_server *s, const ppc_request *reqs, const ui
     }
     if (!s->completed.empty() || s->inflight != 0) return PPC_EBUSY;  // needs an idle server
     const uint64_t b0 = s->batches, r0 = s->batched_requests;
+    const uint64_t d0 = s->host_dispatch_ns, rr0 = s->host_retire_ns;
     std::vector<uint64_t> lat(n, 0);
     std::deque<size_t> backlog;
     uint64_t rejections = 0, total_bytes = 0;
@@ -371,6 +378,8 @@ ppc_status ppc_server_run_trace(ppc_server *s, const ppc_request *reqs, const ui
         stats->batches = s->batches - b0;
         stats->mean_batch = stats->batches ? (double)(s->batched_requests - r0) / stats->batches : 0.0;
         stats->busy_rejections = rejections;
+        stats->host_dispatch_ns = s->host_dispatch_ns - d0;
+        stats->host_retire_ns = s->host_retire_ns - rr0;
         stats->gbps = stats->makespan_ns ? (double)total_bytes / (double)stats->makespan_ns : 0.0;
     }
     return PPC_OK;
