@@ -214,6 +214,50 @@ def served_leg(ppc, torch, synth, dev, plain_gbps, n_requests=100_000, rho=0.5):
     return out
 
 
+def size_sweep(ppc, torch, synth, dev, out_path):
+    """Speed by array length (the paper's main experiment, Section 5.3) on
+    the GPU: for each size, calls are repeated on the same buffer and the
+    same counters (loop-carried, as in Section 5.1) until at least 20 ms
+    and 10 calls; the median call time gives GB/s."""
+    sizes = sorted([1 << i for i in range(1, 31)] + [3 << i for i in range(0, 30)])
+    buf = synth.device_bernoulli(sizes[-1], 0.5, seed=60, device=dev)
+    sink = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    os.makedirs(os.path.dirname(out_path), exist_ok=True)
+    with open(out_path, "w") as out:
+        for n in sizes:
+            row = {"bytes": n}
+            for w in WIDTHS + (0,):
+                counts = torch.zeros(max(w, 1), dtype=torch.int64, device=dev)
+                if w:
+                    call = lambda: ppc.ppc_pospopcnt(w, counts, buf[:n])
+                else:
+                    if n % 16384:
+                        continue
+                    call = lambda: ppc.ppc_read_roofline(sink, buf[:n])
+                for _ in range(3):
+                    call()
+                times = []
+                t_total = 0.0
+                while len(times) < 10 or t_total < 20.0:
+                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    a.record(stream)
+                    call()
+                    b.record(stream)
+                    b.synchronize()
+                    times.append(a.elapsed_time(b))
+                    t_total += times[-1]
+                    if len(times) >= 2000:
+                        break
+                med = sorted(times)[len(times) // 2]
+                key = ("w%d" % w) if w else "read_roofline"
+                row[key + "_us"] = round(med * 1e3, 3)
+                row[key + "_GBps"] = round(n / (med * 1e-3) / 1e9, 3)
+            out.write(json.dumps(row) + "\n")
+            out.flush()
+            log("sweep %11d B: w16 %9.2f us %9.1f GB/s" % (n, row["w16_us"], row["w16_GBps"]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,6 +266,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="length sweep of Section 5.2 (2^i and 3*2^i bytes up to 1.5 GiB) at every "
+                         "width, repeated calls on one buffer as in the paper's harness; writes "
+                         "JSON lines to --sweep-out and exits")
+    ap.add_argument("--sweep-out", default=os.path.join(ROOT, "gpurun_out", "size_sweep.jsonl"))
     ap.add_argument("--profile", action="store_true",
                     help="short fixed run for rocprofv3: 3 plain calls per width, 3 read-roofline "
                          "calls and 3 plain 256 MiB device copies (counter calibration)")
@@ -240,6 +289,9 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     log("device: %s" % torch.cuda.get_device_name(dev))
+    if args.sweep:
+        size_sweep(ppc, torch, synth, dev, args.sweep_out)
+        return
 
     bufs = [synth.device_bernoulli(CALL_BYTES, 0.5, seed=10 + i, device=dev) for i in range(4)]
     counts = {w: torch.zeros(w, dtype=torch.int64, device=dev) for w in WIDTHS}

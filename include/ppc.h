@@ -69,6 +69,21 @@ ppc_status ppc_pospopcnt64(uint64_t *counts, const void *buf, size_t nbytes, voi
 ppc_status ppc_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size_t nbytes,
                          void *stream);
 
+/* Streamed input (Section 4, step 1 and its footnote: counts of several
+ * pieces of one stream add up).  Like ppc_pospopcnt, but bit positions are
+ * relative to a stream that starts `stream_offset` bytes before `buf`:
+ * byte buf[b] feeds counters 8*((stream_offset + b) mod s) .. +7.  Counting
+ * consecutive pieces of a stream, each with its own offset, cut anywhere,
+ * gives exactly the counts of one call over the whole stream. */
+ppc_status ppc_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf, size_t nbytes,
+                            uint64_t stream_offset, void *stream);
+
+/* Conventional population count (the quantity the Harley-Seal scheme of
+ * Section 3.3 computes), on the same carry-save front end: *total (device,
+ * one uint64) += number of set bits in buf[0..nbytes).  Same argument rules
+ * as the plain call. */
+ppc_status ppc_popcount(uint64_t *total, const void *buf, size_t nbytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Launch geometry of the plain call.  `waves` caps the number of wavefronts
  * the grid holds (0 = the library default: 8 per compute unit);

@@ -94,6 +94,8 @@ def _declare(lib):
         "ppc_pospopcnt16": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
         "ppc_pospopcnt32": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
         "ppc_pospopcnt64": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
+        "ppc_pospopcnt_at": ([_c_uint, _c_ptr, _c_ptr, _c_size, ctypes.c_uint64, _c_ptr], ctypes.c_int),
+        "ppc_popcount": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
         "ppc_set_plain_geometry": ([_c_uint, _c_uint], ctypes.c_int),
         "ppc_get_plain_geometry": ([ctypes.POINTER(_c_uint), ctypes.POINTER(_c_uint)], ctypes.c_int),
         "ppc_read_roofline": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
@@ -201,6 +203,16 @@ def ppc_pospopcnt32(counts, buf, nbytes=None, stream=None):
 def ppc_pospopcnt64(counts, buf, nbytes=None, stream=None):
     _check(lib().ppc_pospopcnt64(_counts_ptr(counts, 64), _ptr(buf), _nbytes(buf, nbytes),
                                  _stream(stream)), "ppc_pospopcnt64")
+
+
+def ppc_pospopcnt_at(width, counts, buf, nbytes=None, stream_offset=0, stream=None):
+    _check(lib().ppc_pospopcnt_at(int(width), _counts_ptr(counts, width), _ptr(buf), _nbytes(buf, nbytes),
+                                  int(stream_offset), _stream(stream)), "ppc_pospopcnt_at")
+
+
+def ppc_popcount(total, buf, nbytes=None, stream=None):
+    _check(lib().ppc_popcount(_counts_ptr(total, 1), _ptr(buf), _nbytes(buf, nbytes), _stream(stream)),
+           "ppc_popcount")
 
 
 def ppc_set_plain_geometry(waves: int, waves_per_block: int):

@@ -37,9 +37,9 @@ struct PlainArgs {
     const uint8_t *edge0;       // head bytes (lanes 0..31 of wave 0)
     const uint8_t *edge1;       // tail bytes (lanes 32..63 of wave 0)
     uint32_t edge0_len, edge1_len;
-    unsigned long long *counts; // w uint64 counters
-    uint32_t width;             // 8, 16, 32, 64
-    uint32_t m;                 // buf mod (w/8)
+    unsigned long long *counts; // w uint64 counters (one for the total popcount)
+    uint32_t width;             // 8, 16, 32, 64; 0 = total popcount
+    uint32_t m;                 // slot of buf's first byte subtracted from address slots (mod w/8)
 };
 
 // WPB: waves per block; NT: streaming loads (large inputs).  Each wave
@@ -67,7 +67,16 @@ __global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
     __shared__ uint32_t part[WPB][kWave];
     part[wib][lane] = acc;
     __syncthreads();
-    if (threadIdx.x < a.width) {
+    if (a.width == 0) {  // conventional population count: every position into counts[0]
+        if (wib == 0) {
+            uint64_t v = 0;
+#pragma unroll
+            for (int wv = 0; wv < WPB; ++wv) v += part[wv][lane];
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
+            if (lane == 0 && v) atomicAdd(a.counts, (unsigned long long)v);
+        }
+    } else if (threadIdx.x < a.width) {
         const uint32_t s = a.width >> 3;
         const uint32_t j = threadIdx.x;
         const uint32_t k = j & 7u;
@@ -210,14 +219,18 @@ static ppc_status plain_launch_range(unsigned width, uint64_t *counts, const uin
 static constexpr uint64_t kMaxTilesPerWave = 1ull << 20;
 static constexpr size_t kMaxLaunchBytes = (size_t)1 << 40;
 
-ppc_status plain_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, hipStream_t st) {
-    if (!(width == 8 || width == 16 || width == 32 || width == 64)) return PPC_EINVAL;
+// Positions are counted relative to a stream start `offset` bytes before
+// buf: byte buf[b] feeds slot (offset + b) mod s.  Address slot a of byte
+// buf[b] is (buf + b) mod 8, so the fold subtracts m = (buf - offset) mod s.
+ppc_status plain_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, uint64_t offset,
+                              hipStream_t st) {
+    if (!(width == 0 || width == 8 || width == 16 || width == 32 || width == 64)) return PPC_EINVAL;
     if (counts == nullptr || ((uintptr_t)counts & 7u) != 0) return PPC_EINVAL;
     if (nbytes == 0) return PPC_OK;
     if (buf == nullptr) return PPC_EINVAL;
     const uint8_t *p = static_cast<const uint8_t *>(buf);
-    const uint32_t s = width / 8u;
-    const uint32_t m = (uint32_t)((uintptr_t)p % s);
+    const uint32_t s = width ? width / 8u : 1u;
+    const uint32_t m = (uint32_t)(((uintptr_t)p - (uintptr_t)(offset % 8u) + 8u) % s);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
     const size_t tile_bytes = (size_t)kTileChunks * 16u;
@@ -231,6 +244,11 @@ ppc_status plain_pospopcnt(unsigned width, uint64_t *counts, const void *buf, si
         done += len;
     }
     return PPC_OK;
+}
+
+ppc_status plain_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, hipStream_t st) {
+    if (width == 0) return PPC_EINVAL;
+    return plain_pospopcnt_at(width, counts, buf, nbytes, 0, st);
 }
 
 }  // namespace ppc
@@ -253,6 +271,16 @@ ppc_status ppc_pospopcnt32(uint64_t *counts, const void *buf, size_t nbytes, voi
 }
 ppc_status ppc_pospopcnt64(uint64_t *counts, const void *buf, size_t nbytes, void *stream) {
     return plain_pospopcnt(64, counts, buf, nbytes, (hipStream_t)stream);
+}
+
+ppc_status ppc_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf, size_t nbytes,
+                            uint64_t stream_offset, void *stream) {
+    if (width == 0) return PPC_EINVAL;
+    return plain_pospopcnt_at(width, counts, buf, nbytes, stream_offset, (hipStream_t)stream);
+}
+
+ppc_status ppc_popcount(uint64_t *total, const void *buf, size_t nbytes, void *stream) {
+    return plain_pospopcnt_at(0, total, buf, nbytes, 0, (hipStream_t)stream);
 }
 
 ppc_status ppc_set_plain_geometry(unsigned waves, unsigned waves_per_block) {

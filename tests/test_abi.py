@@ -77,3 +77,15 @@ def test_roofline_validation(lib):
     assert lib.ppc_read_roofline(None, 0x1000, 16384, None) == 1
     assert lib.ppc_read_roofline(0x1000, 0x1001, 16384, None) == 1
     assert lib.ppc_read_roofline(0x1000, 0x1000, 100, None) == 1
+
+
+def test_stream_and_popcount_validation(lib):
+    fake = 0x1000
+    assert lib.ppc_pospopcnt_at(0, fake, fake, 10, 3, None) == 1   # width 0 is not a width
+    assert lib.ppc_pospopcnt_at(24, fake, fake, 10, 3, None) == 1
+    assert lib.ppc_pospopcnt_at(16, fake + 2, fake, 10, 3, None) == 1
+    assert lib.ppc_pospopcnt_at(16, fake, None, 0, 3, None) == 0
+    assert lib.ppc_popcount(None, fake, 10, None) == 1
+    assert lib.ppc_popcount(fake + 4, fake, 10, None) == 1
+    assert lib.ppc_popcount(fake, None, 10, None) == 1
+    assert lib.ppc_popcount(fake, None, 0, None) == 0
