@@ -271,6 +271,9 @@ def main():
                          "width, repeated calls on one buffer as in the paper's harness; writes "
                          "JSON lines to --sweep-out and exits")
     ap.add_argument("--sweep-out", default=os.path.join(ROOT, "gpurun_out", "size_sweep.jsonl"))
+    ap.add_argument("--ablation", action="store_true",
+                    help="time the three accumulation schedules (ppc_pospopcnt_variant 0/1/2) on "
+                         "256 MiB at w = 16 and exit (short: also the command to profile them)")
     ap.add_argument("--profile", action="store_true",
                     help="short fixed run for rocprofv3: 3 plain calls per width, 3 read-roofline "
                          "calls and 3 plain 256 MiB device copies (counter calibration)")
@@ -291,6 +294,18 @@ def main():
     log("device: %s" % torch.cuda.get_device_name(dev))
     if args.sweep:
         size_sweep(ppc, torch, synth, dev, args.sweep_out)
+        return
+    if args.ablation:
+        abufs = [synth.device_bernoulli(CALL_BYTES, 0.5, seed=30 + i, device=dev) for i in range(4)]
+        c16 = torch.zeros(16, dtype=torch.int64, device=dev)
+        res = {}
+        for v in (0, 1, 2):
+            ms = time_calls(lambda b, i: ppc.ppc_pospopcnt_variant(v, 16, c16, b), abufs, 12, torch)
+            med = sorted(ms)[len(ms) // 2]
+            res["variant%d" % v] = {"us": round(med * 1e3, 2),
+                                    "GBps": round(CALL_BYTES / (med * 1e-3) / 1e9, 1)}
+            log("variant %d: %.2f us, %.1f GB/s" % (v, med * 1e3, CALL_BYTES / (med * 1e-3) / 1e9))
+        print(json.dumps({"ablation_256MiB_w16": res}), flush=True)
         return
 
     bufs = [synth.device_bernoulli(CALL_BYTES, 0.5, seed=10 + i, device=dev) for i in range(4)]

@@ -84,6 +84,18 @@ ppc_status ppc_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf, s
  * as the plain call. */
 ppc_status ppc_popcount(uint64_t *total, const void *buf, size_t nbytes, void *stream);
 
+/* Accumulation-schedule variants of the plain call, for measurement: the
+ * same exact counts computed three ways.  0 = the library path (carry-save
+ * front end + bit-parallel accumulation of the weight-16 plane, Sections
+ * 4.2-4.5); 1 = carry-save front end + per-position accumulation of the
+ * weight-16 plane (the O(w) schedule of Klarqvist et al., Algorithm 2);
+ * 2 = no carry-save front end (every bit added to its position counter, the
+ * loop of Fig. 2 across lanes).  Same argument rules as ppc_pospopcnt;
+ * variants 1 and 2 reject (PPC_EINVAL) inputs that would give a wave more
+ * than 2^20 tiles of 16 KiB in one launch. */
+ppc_status ppc_pospopcnt_variant(unsigned variant, unsigned width, uint64_t *counts, const void *buf,
+                                 size_t nbytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Launch geometry of the plain call.  `waves` caps the number of wavefronts
  * the grid holds (0 = the library default: 8 per compute unit);

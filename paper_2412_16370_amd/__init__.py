@@ -96,6 +96,7 @@ def _declare(lib):
         "ppc_pospopcnt64": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
         "ppc_pospopcnt_at": ([_c_uint, _c_ptr, _c_ptr, _c_size, ctypes.c_uint64, _c_ptr], ctypes.c_int),
         "ppc_popcount": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
+        "ppc_pospopcnt_variant": ([_c_uint, _c_uint, _c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
         "ppc_set_plain_geometry": ([_c_uint, _c_uint], ctypes.c_int),
         "ppc_get_plain_geometry": ([ctypes.POINTER(_c_uint), ctypes.POINTER(_c_uint)], ctypes.c_int),
         "ppc_read_roofline": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
@@ -213,6 +214,11 @@ def ppc_pospopcnt_at(width, counts, buf, nbytes=None, stream_offset=0, stream=No
 def ppc_popcount(total, buf, nbytes=None, stream=None):
     _check(lib().ppc_popcount(_counts_ptr(total, 1), _ptr(buf), _nbytes(buf, nbytes), _stream(stream)),
            "ppc_popcount")
+
+
+def ppc_pospopcnt_variant(variant, width, counts, buf, nbytes=None, stream=None):
+    _check(lib().ppc_pospopcnt_variant(int(variant), int(width), _counts_ptr(counts, width), _ptr(buf),
+                                       _nbytes(buf, nbytes), _stream(stream)), "ppc_pospopcnt_variant")
 
 
 def ppc_set_plain_geometry(waves: int, waves_per_block: int):
