@@ -81,6 +81,19 @@ def time_calls(fn, bufs, reps, torch):
     return [a.elapsed_time(b) for a, b in ev]
 
 
+def dispatch_timed(fn, bufs, reps, torch):
+    """Run fn(buf, start_event, stop_event) over the buffers in rotation;
+    the library's dispatch records the events, so each interval is one
+    kernel's execution.  Returns per-call ms."""
+    import paper_2412_16370_amd as ppc
+
+    ev = [(ppc.HipEvent(), ppc.HipEvent()) for _ in range(reps)]
+    for i in range(reps):
+        fn(bufs[i % len(bufs)], ev[i][0], ev[i][1])
+    torch.cuda.synchronize()
+    return [a.elapsed_ms(b) for a, b in ev]
+
+
 def cpu_baseline(seconds_target=15.0):
     """The oracle on this host: multithreaded word loop over a bounded
     sample of the same workload (256 MiB of Bernoulli(0.5) bytes at each
@@ -335,22 +348,23 @@ def main():
         step_calls(i)
     torch.cuda.synchronize()
 
-    # whole-job timing: K steps between two synchronisations
-    stream = torch.cuda.current_stream()
-    ev = []
+    # whole-job timing: K steps between two synchronisations; every launch
+    # carries a HIP event pair that its own dispatch records (kernel start
+    # and end on the launch stream)
+    ev = [(w, ppc.HipEvent(), ppc.HipEvent()) for i in range(args.steps) for w in WIDTHS]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
+    k = 0
     for i in range(args.steps):
         for j, w in enumerate(WIDTHS):
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record(stream)
-            ppc.ppc_pospopcnt(w, counts[w], bufs[(i + j) % 4])
-            b.record(stream)
-            ev.append((w, a, b))
+            _, a, b = ev[k]
+            ppc.ppc_pospopcnt_timed(w, counts[w], bufs[(i + j) % 4], start_event=a, stop_event=b)
+            k += 1
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per_call = {w: [] for w in WIDTHS}
     for w, a, b in ev:
-        per_call[w].append(a.elapsed_time(b))
+        per_call[w].append(a.elapsed_ms(b))
     all_ms = [x for v in per_call.values() for x in v]
     avg_ms = sum(all_ms) / len(all_ms)
     total_bytes = args.steps * len(WIDTHS) * CALL_BYTES
@@ -362,7 +376,8 @@ def main():
     sink = torch.zeros(1, dtype=torch.int64, device=dev)
     for i in range(args.warmup):
         ppc.ppc_read_roofline(sink, bufs[i % 4])
-    rl = time_calls(lambda b, i: ppc.ppc_read_roofline(sink, b), bufs, 4 * args.steps, torch)
+    rl = dispatch_timed(lambda b, e0, e1: ppc.ppc_read_roofline_timed(sink, b, start_event=e0, stop_event=e1),
+                        bufs, 4 * args.steps, torch)
     rl_gbps = CALL_BYTES / (sum(rl) / len(rl) * 1e-3) / 1e9
     log("read roofline: %.1f GB/s" % rl_gbps)
 
@@ -371,7 +386,8 @@ def main():
     for p in (0.01, 0.99):
         dbufs = [synth.device_bernoulli(CALL_BYTES, p, seed=20 + i, device=dev) for i in range(4)]
         c16 = torch.zeros(16, dtype=torch.int64, device=dev)
-        ms = time_calls(lambda b, i: ppc.ppc_pospopcnt16(c16, b), dbufs, 4 * args.steps, torch)
+        ms = dispatch_timed(lambda b, e0, e1: ppc.ppc_pospopcnt_timed(16, c16, b, start_event=e0, stop_event=e1),
+                            dbufs, 4 * args.steps, torch)
         density[str(p)] = round(CALL_BYTES / (sum(ms) / len(ms) * 1e-3) / 1e9, 1)
         del dbufs
     density["0.5"] = round(CALL_BYTES / (sum(per_call[16]) / len(per_call[16]) * 1e-3) / 1e9, 1)

@@ -69,6 +69,17 @@ ppc_status ppc_pospopcnt64(uint64_t *counts, const void *buf, size_t nbytes, voi
 ppc_status ppc_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size_t nbytes,
                          void *stream);
 
+/* The plain call with kernel timing: `start_event` / `stop_event` (hipEvent_t
+ * as void*, created by the caller, either may be NULL) are recorded by the
+ * kernel dispatch itself (AMD's extended launch), so the interval between
+ * them is the kernel's execution time, without the gaps that events
+ * recorded separately on the stream would add.  If the call needs several
+ * launches (more than the per-launch limit of bytes), start is recorded by
+ * the first and stop by the last.  If nothing is launched (nbytes == 0) the
+ * events are not recorded. */
+ppc_status ppc_pospopcnt_timed(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, void *stream,
+                               void *start_event, void *stop_event);
+
 /* Streamed input (Section 4, step 1 and its footnote: counts of several
  * pieces of one stream add up).  Like ppc_pospopcnt, but bit positions are
  * relative to a stream that starts `stream_offset` bytes before `buf`:
@@ -115,6 +126,11 @@ ppc_status ppc_get_plain_geometry(unsigned *waves, unsigned *waves_per_block);
  * can reach.
  * ---------------------------------------------------------------------- */
 ppc_status ppc_read_roofline(uint64_t *sink, const void *buf, size_t nbytes, void *stream);
+
+/* The same, with events recorded by the kernel dispatch (see
+ * ppc_pospopcnt_timed). */
+ppc_status ppc_read_roofline_timed(uint64_t *sink, const void *buf, size_t nbytes, void *stream,
+                                   void *start_event, void *stop_event);
 
 
 /* ------------------------------------------------------------------------
@@ -187,7 +203,7 @@ ppc_status ppc_plan_destroy(ppc_plan *plan);
  * is used from one host thread at a time.
  * ---------------------------------------------------------------------- */
 typedef struct ppc_server_cfg {
-    uint32_t n_streams;      /* batches in flight at once (0 = 4)             */
+    uint32_t n_streams;      /* batches in flight at once (0 = 3)             */
     uint32_t max_batch;      /* requests per batch (0 = 1024)                 */
     uint32_t max_inflight;   /* result slots = admitted requests (0 = 16384)  */
     uint32_t tiles_per_item; /* 16 KiB tiles per work item (0 = 16)           */

@@ -96,6 +96,8 @@ def _declare(lib):
         "ppc_pospopcnt64": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
         "ppc_pospopcnt_at": ([_c_uint, _c_ptr, _c_ptr, _c_size, ctypes.c_uint64, _c_ptr], ctypes.c_int),
         "ppc_popcount": ([_c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
+        "ppc_pospopcnt_timed": ([_c_uint, _c_ptr, _c_ptr, _c_size, _c_ptr, _c_ptr, _c_ptr], ctypes.c_int),
+        "ppc_read_roofline_timed": ([_c_ptr, _c_ptr, _c_size, _c_ptr, _c_ptr, _c_ptr], ctypes.c_int),
         "ppc_pospopcnt_variant": ([_c_uint, _c_uint, _c_ptr, _c_ptr, _c_size, _c_ptr], ctypes.c_int),
         "ppc_set_plain_geometry": ([_c_uint, _c_uint], ctypes.c_int),
         "ppc_get_plain_geometry": ([ctypes.POINTER(_c_uint), ctypes.POINTER(_c_uint)], ctypes.c_int),
@@ -219,6 +221,72 @@ def ppc_popcount(total, buf, nbytes=None, stream=None):
 def ppc_pospopcnt_variant(variant, width, counts, buf, nbytes=None, stream=None):
     _check(lib().ppc_pospopcnt_variant(int(variant), int(width), _counts_ptr(counts, width), _ptr(buf),
                                        _nbytes(buf, nbytes), _stream(stream)), "ppc_pospopcnt_variant")
+
+
+_hip = None
+
+
+def _hiprt():
+    """The HIP runtime libppc.so itself uses (loaded by soname, so it is the
+    process's one runtime, torch's when torch is loaded)."""
+    global _hip
+    if _hip is None:
+        lib()
+        h = ctypes.CDLL("libamdhip64.so.7")
+        h.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        h.hipEventCreate.restype = ctypes.c_int
+        h.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        h.hipEventElapsedTime.restype = ctypes.c_int
+        h.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        h.hipEventDestroy.restype = ctypes.c_int
+        _hip = h
+    return _hip
+
+
+class HipEvent:
+    """A timing hipEvent_t for the *_timed calls, which record it from the
+    kernel dispatch itself."""
+
+    def __init__(self):
+        self.handle = ctypes.c_void_p()
+        if _hiprt().hipEventCreate(ctypes.byref(self.handle)) != 0:
+            raise RuntimeError("hipEventCreate failed")
+
+    def elapsed_ms(self, end: "HipEvent") -> float:
+        """Milliseconds from this event to `end`; both must have completed."""
+        ms = ctypes.c_float()
+        rc = _hiprt().hipEventElapsedTime(ctypes.byref(ms), self.handle, end.handle)
+        if rc != 0:
+            raise RuntimeError("hipEventElapsedTime failed (%d)" % rc)
+        return ms.value
+
+    def __del__(self):
+        if self.handle and _hip is not None:
+            _hip.hipEventDestroy(self.handle)
+            self.handle = ctypes.c_void_p()
+
+
+def _event(e):
+    if e is None:
+        return None
+    if isinstance(e, int):
+        return e
+    if isinstance(e, HipEvent):
+        return e.handle.value
+    raise TypeError("expected a HipEvent or a raw hipEvent_t address")
+
+
+def ppc_pospopcnt_timed(width, counts, buf, nbytes=None, stream=None, start_event=None, stop_event=None):
+    """Plain call whose kernel dispatch records the given HipEvent pair at
+    its start and end."""
+    _check(lib().ppc_pospopcnt_timed(int(width), _counts_ptr(counts, width), _ptr(buf), _nbytes(buf, nbytes),
+                                     _stream(stream), _event(start_event), _event(stop_event)),
+           "ppc_pospopcnt_timed")
+
+
+def ppc_read_roofline_timed(sink, buf, nbytes=None, stream=None, start_event=None, stop_event=None):
+    _check(lib().ppc_read_roofline_timed(_ptr(sink), _ptr(buf), _nbytes(buf, nbytes), _stream(stream),
+                                         _event(start_event), _event(stop_event)), "ppc_read_roofline_timed")
 
 
 def ppc_set_plain_geometry(waves: int, waves_per_block: int):

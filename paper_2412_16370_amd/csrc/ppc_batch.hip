@@ -59,10 +59,10 @@ __device__ __forceinline__ void fold_and_add(uint32_t acc, uint32_t width, uint3
     if (lane < width && v != 0u) atomicAdd(counts + fold_position(lane, width, m), (unsigned long long)v);
 }
 
-template <int WPB>
-__global__ __launch_bounds__(WPB *kWave) void batched_kernel(const ArrayInfo *__restrict__ arrays,
-                                                             const WorkItem *__restrict__ items, uint32_t n_items,
-                                                             uint32_t *cursor) {
+// The persistent loop of one wave: take items from the cursor until it
+// passes n_items.
+__device__ __forceinline__ void run_items(const ArrayInfo *__restrict__ arrays, const WorkItem *__restrict__ items,
+                                          uint32_t n_items, uint32_t *cursor) {
     const uint32_t lane = __lane_id();
     uint32_t ticket = 0;
     if (lane == 0) ticket = atomicAdd(cursor, 1u);
@@ -87,6 +87,70 @@ __global__ __launch_bounds__(WPB *kWave) void batched_kernel(const ArrayInfo *__
         fold_and_add(acc, ai.width, ai.m, ai.counts);
         cur = (uint32_t)__builtin_amdgcn_readfirstlane((int)next);
     }
+}
+
+template <int WPB>
+__global__ __launch_bounds__(WPB *kWave) void batched_kernel(const ArrayInfo *__restrict__ arrays,
+                                                             const WorkItem *__restrict__ items, uint32_t n_items,
+                                                             uint32_t *cursor) {
+    run_items(arrays, items, n_items, cursor);
+}
+
+// ---- server batch sequence (captured once per stream) ---------------------
+__global__ void stage_copy_kernel(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, uint32_t items_off) {
+    const BatchHeader h = *reinterpret_cast<const BatchHeader *>(src);
+    const uint32_t n16_arrays = (uint32_t)((sizeof(BatchHeader) + (size_t)h.n_arrays * sizeof(ArrayInfo)) / 16u);
+    const uint32_t n16_items = (uint32_t)((size_t)h.n_items * sizeof(WorkItem) / 16u);
+    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
+    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
+    const uint32_t off16 = items_off / 16u;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n16_arrays + n16_items; i += gridDim.x * blockDim.x) {
+        const uint32_t j = i < n16_arrays ? i : off16 + (i - n16_arrays);
+        d4[j] = s4[j];
+    }
+}
+
+template <int WPB>
+__global__ __launch_bounds__(WPB *kWave) void served_batch_kernel(const uint8_t *__restrict__ stage, uint32_t items_off,
+                                                                  uint32_t *cursor) {
+    const BatchHeader *h = reinterpret_cast<const BatchHeader *>(stage);
+    run_items(reinterpret_cast<const ArrayInfo *>(stage + sizeof(BatchHeader)),
+              reinterpret_cast<const WorkItem *>(stage + items_off), h->n_items, cursor);
+}
+
+__global__ void served_epilogue_kernel(const uint8_t *__restrict__ stage, unsigned long long *counts,
+                                       uint64_t *results, uint32_t *cursor) {
+    const uint32_t n = reinterpret_cast<const BatchHeader *>(stage)->n_arrays * 64u;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        results[i] = counts[i];
+        counts[i] = 0ull;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *cursor = 0u;
+}
+
+hipError_t capture_served_graph(hipGraph_t *graph, hipGraphExec_t *exec, const uint8_t *stage_host,
+                                uint8_t *stage_dev, size_t items_off, size_t stage_bytes,
+                                unsigned long long *counts_dev, uint64_t *results_host, uint32_t *cursor_dev,
+                                uint32_t waves) {
+    (void)stage_bytes;
+    hipStream_t cap = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        constexpr int kWpb = 4;
+        hipLaunchKernelGGL(stage_copy_kernel, dim3(16), dim3(256), 0, cap, stage_host, stage_dev, (uint32_t)items_off);
+        hipLaunchKernelGGL(served_batch_kernel<kWpb>, dim3((waves + kWpb - 1) / kWpb), dim3(kWpb * kWave), 0, cap,
+                           (const uint8_t *)stage_dev, (uint32_t)items_off, cursor_dev);
+        hipLaunchKernelGGL(served_epilogue_kernel, dim3(64), dim3(256), 0, cap, (const uint8_t *)stage_dev,
+                           counts_dev, results_host, cursor_dev);
+        const hipError_t launched = hipGetLastError();
+        e = hipStreamEndCapture(cap, graph);
+        if (e == hipSuccess) e = launched;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cap);
+    return e;
 }
 
 bool make_array_info(ArrayInfo &ai, const void *buf, uint64_t nbytes, uint64_t *counts, uint32_t width) {

@@ -33,6 +33,14 @@ struct WorkItem {
 };
 static_assert(sizeof(WorkItem) == 16, "WorkItem layout");
 
+// Header of a server batch in its staging buffer (64 bytes): the
+// ArrayInfo table follows at byte 64, the WorkItem table at a fixed offset.
+struct BatchHeader {
+    uint32_t n_arrays, n_items;
+    uint32_t reserved[14];
+};
+static_assert(sizeof(BatchHeader) == 64, "BatchHeader layout");
+
 // Per-item tile cap: keeps every per-wave 32-bit count below 2^31.
 constexpr uint32_t kMaxItemTiles = 1u << 20;
 
@@ -51,5 +59,16 @@ void sort_items_lpt(std::vector<WorkItem> &items);
 hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, uint32_t n_items,
                           uint32_t *cursor_dev, uint32_t waves, hipStream_t st,
                           unsigned long long *clear = nullptr, uint64_t n_clear = 0);
+
+// Captures the fixed launch sequence of one server stream into a graph:
+// copy the batch tables (sizes read from the header) from pinned host
+// memory to the device, run the persistent kernel over them, then copy the
+// first n_arrays * 64 counters to pinned host memory, clear them and reset
+// the cursor for the next batch.  Per batch the host only fills the staging
+// buffer and launches the graph.
+hipError_t capture_served_graph(hipGraph_t *graph, hipGraphExec_t *exec, const uint8_t *stage_host,
+                                uint8_t *stage_dev, size_t items_off, size_t stage_bytes,
+                                unsigned long long *counts_dev, uint64_t *results_host, uint32_t *cursor_dev,
+                                uint32_t waves);
 
 }  // namespace ppc

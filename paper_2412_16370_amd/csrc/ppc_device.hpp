@@ -125,6 +125,28 @@ __device__ __forceinline__ uint32_t wave_in_block() {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
 }
 
+// Partner value for lane ^ S inside a 32-lane half.  DPP row operations
+// where gfx950 has one (xor 1 and 2 by quad permutation, xor 8 by a row
+// rotation by 8, xor 4 by a left and a right row shift merged per bank);
+// the LDS-pipe swizzle for xor 16.
+template <int S>
+__device__ __forceinline__ uint32_t partner_xor(uint32_t x) {
+    if constexpr (S == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+    } else if constexpr (S == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    } else if constexpr (S == 4) {
+        // banks 0 and 2 of each row (lanes 0-3, 8-11) read lane + 4; banks 1 and
+        // 3 (lanes 4-7, 12-15) read lane - 4
+        const int up = __builtin_amdgcn_mov_dpp((int)x, 0x104, 0xF, 0xF, true);   // row_shl:4
+        return (uint32_t)__builtin_amdgcn_update_dpp(up, (int)x, 0x114, 0xF, 0xA, false);  // row_shr:4
+    } else if constexpr (S == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_ror:8
+    } else {
+        return swz_xor<S>(x);
+    }
+}
+
 // One stage of a 32x32 bit-matrix transpose across the lanes of each 32-lane
 // half (the recursive block transpose of Section 4.5, done across lanes
 // instead of inside one register).  Row = lane, column = bit.  The rows with
@@ -132,7 +154,7 @@ __device__ __forceinline__ uint32_t wave_in_block() {
 // columns with (col & S) == 0.
 template <int S>
 __device__ __forceinline__ uint32_t transpose_stage(uint32_t x, uint32_t take_mask, uint32_t rot) {
-    uint32_t partner = swz_xor<S>(x);
+    uint32_t partner = partner_xor<S>(x);
     uint32_t t = __builtin_amdgcn_alignbit(partner, partner, rot);  // rotate right
     return (take_mask & t) | (~take_mask & x);
 }

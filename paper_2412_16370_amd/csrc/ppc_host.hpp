@@ -14,6 +14,12 @@ int device_cus(int device);
 // Plain call on an explicit stream (argument checks included).
 ppc_status plain_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, hipStream_t st);
 
+// Plain call with positions relative to a stream start `offset` bytes
+// before buf (width 0 = total popcount into counts[0]); optional events
+// recorded by the first and last kernel dispatch.
+ppc_status plain_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, uint64_t offset,
+                              hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
+
 // Wave cap of the plain call's grid on a device.
 unsigned plain_wave_cap(int device);
 

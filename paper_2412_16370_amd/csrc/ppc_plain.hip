@@ -17,6 +17,7 @@
 //                transposes and popcounts (Section 4.5).
 //   f_w        : per-block LDS partials are folded to w positions relative
 //                to `buf` and added to `counts` with 64-bit atomics.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -155,19 +156,28 @@ static std::atomic<unsigned> g_plain_wpb{8};
 // Inputs at least this large use streaming loads.
 static constexpr size_t kStreamBytes = (size_t)32 << 20;
 
+// Launch events: when given, the start/stop events are recorded by the
+// kernel dispatch itself (hipExtLaunchKernel), so their interval is the
+// kernel's own execution time.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 template <bool NT>
-static hipError_t launch_plain_nt(const PlainArgs &a, unsigned blocks, unsigned wpb, hipStream_t st) {
+static hipError_t launch_plain_nt(const PlainArgs &a, unsigned blocks, unsigned wpb, hipStream_t st,
+                                  LaunchEvents ev) {
     if (wpb == 2)
-        hipLaunchKernelGGL((pospop_plain_kernel<2, NT>), dim3(blocks), dim3(128), 0, st, a);
+        hipExtLaunchKernelGGL((pospop_plain_kernel<2, NT>), dim3(blocks), dim3(128), 0, st, ev.start, ev.stop, 0, a);
     else if (wpb == 4)
-        hipLaunchKernelGGL((pospop_plain_kernel<4, NT>), dim3(blocks), dim3(256), 0, st, a);
+        hipExtLaunchKernelGGL((pospop_plain_kernel<4, NT>), dim3(blocks), dim3(256), 0, st, ev.start, ev.stop, 0, a);
     else
-        hipLaunchKernelGGL((pospop_plain_kernel<8, NT>), dim3(blocks), dim3(512), 0, st, a);
+        hipExtLaunchKernelGGL((pospop_plain_kernel<8, NT>), dim3(blocks), dim3(512), 0, st, ev.start, ev.stop, 0, a);
     return hipGetLastError();
 }
 
-static hipError_t launch_plain(const PlainArgs &a, bool nt, unsigned blocks, unsigned wpb, hipStream_t st) {
-    return nt ? launch_plain_nt<true>(a, blocks, wpb, st) : launch_plain_nt<false>(a, blocks, wpb, st);
+static hipError_t launch_plain(const PlainArgs &a, bool nt, unsigned blocks, unsigned wpb, hipStream_t st,
+                               LaunchEvents ev) {
+    return nt ? launch_plain_nt<true>(a, blocks, wpb, st, ev) : launch_plain_nt<false>(a, blocks, wpb, st, ev);
 }
 
 unsigned plain_wave_cap(int device) {
@@ -178,7 +188,7 @@ unsigned plain_wave_cap(int device) {
 
 // One launch over a range the caller has sized with kMaxTilesPerWave.
 static ppc_status plain_launch_range(unsigned width, uint64_t *counts, const uint8_t *buf, size_t nbytes,
-                                     uint32_t m, hipStream_t st) {
+                                     uint32_t m, hipStream_t st, LaunchEvents ev) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
     const uintptr_t b0 = (uintptr_t)buf;
@@ -209,7 +219,7 @@ static ppc_status plain_launch_range(unsigned width, uint64_t *counts, const uin
     const unsigned wpb = g_plain_wpb.load(std::memory_order_relaxed);
     uint64_t waves = std::min<uint64_t>(std::max<uint32_t>(a.n_tiles, 1u), plain_wave_cap(dev));
     const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
-    return launch_plain(a, nbytes >= kStreamBytes, blocks, wpb, st) == hipSuccess ? PPC_OK : PPC_EDEVICE;
+    return launch_plain(a, nbytes >= kStreamBytes, blocks, wpb, st, ev) == hipSuccess ? PPC_OK : PPC_EDEVICE;
 }
 
 // Per-wave counts are 32-bit: a wave adds at most 64 lanes x 2 dwords x 16
@@ -223,7 +233,7 @@ static constexpr size_t kMaxLaunchBytes = (size_t)1 << 40;
 // buf: byte buf[b] feeds slot (offset + b) mod s.  Address slot a of byte
 // buf[b] is (buf + b) mod 8, so the fold subtracts m = (buf - offset) mod s.
 ppc_status plain_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, uint64_t offset,
-                              hipStream_t st) {
+                              hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop) {
     if (!(width == 0 || width == 8 || width == 16 || width == 32 || width == 64)) return PPC_EINVAL;
     if (counts == nullptr || ((uintptr_t)counts & 7u) != 0) return PPC_EINVAL;
     if (nbytes == 0) return PPC_OK;
@@ -239,7 +249,10 @@ ppc_status plain_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf,
     size_t done = 0;
     while (done < nbytes) {  // pieces start at multiples of 8 from buf: same m
         const size_t len = std::min(piece, nbytes - done);
-        ppc_status rc = plain_launch_range(width, counts, p + done, len, m, st);
+        LaunchEvents ev;  // start on the first launch, stop on the last
+        if (done == 0) ev.start = ev_start;
+        if (done + len == nbytes) ev.stop = ev_stop;
+        ppc_status rc = plain_launch_range(width, counts, p + done, len, m, st, ev);
         if (rc != PPC_OK) return rc;
         done += len;
     }
@@ -248,7 +261,7 @@ ppc_status plain_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf,
 
 ppc_status plain_pospopcnt(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, hipStream_t st) {
     if (width == 0) return PPC_EINVAL;
-    return plain_pospopcnt_at(width, counts, buf, nbytes, 0, st);
+    return plain_pospopcnt_at(width, counts, buf, nbytes, 0, st, nullptr, nullptr);
 }
 
 }  // namespace ppc
@@ -276,11 +289,18 @@ ppc_status ppc_pospopcnt64(uint64_t *counts, const void *buf, size_t nbytes, voi
 ppc_status ppc_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf, size_t nbytes,
                             uint64_t stream_offset, void *stream) {
     if (width == 0) return PPC_EINVAL;
-    return plain_pospopcnt_at(width, counts, buf, nbytes, stream_offset, (hipStream_t)stream);
+    return plain_pospopcnt_at(width, counts, buf, nbytes, stream_offset, (hipStream_t)stream, nullptr, nullptr);
+}
+
+ppc_status ppc_pospopcnt_timed(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, void *stream,
+                               void *start_event, void *stop_event) {
+    if (width == 0) return PPC_EINVAL;
+    return plain_pospopcnt_at(width, counts, buf, nbytes, 0, (hipStream_t)stream, (hipEvent_t)start_event,
+                              (hipEvent_t)stop_event);
 }
 
 ppc_status ppc_popcount(uint64_t *total, const void *buf, size_t nbytes, void *stream) {
-    return plain_pospopcnt_at(0, total, buf, nbytes, 0, (hipStream_t)stream);
+    return plain_pospopcnt_at(0, total, buf, nbytes, 0, (hipStream_t)stream, nullptr, nullptr);
 }
 
 ppc_status ppc_set_plain_geometry(unsigned waves, unsigned waves_per_block) {
@@ -300,7 +320,8 @@ ppc_status ppc_get_plain_geometry(unsigned *waves, unsigned *waves_per_block) {
     return PPC_OK;
 }
 
-ppc_status ppc_read_roofline(uint64_t *sink, const void *buf, size_t nbytes, void *stream) {
+ppc_status ppc_read_roofline_timed(uint64_t *sink, const void *buf, size_t nbytes, void *stream,
+                                   void *start_event, void *stop_event) {
     if (sink == nullptr || ((uintptr_t)sink & 7u) != 0) return PPC_EINVAL;
     if (nbytes == 0) return PPC_OK;
     if (buf == nullptr || ((uintptr_t)buf & 15u) != 0 || (nbytes & 15u) != 0) return PPC_EINVAL;
@@ -316,13 +337,18 @@ ppc_status ppc_read_roofline(uint64_t *sink, const void *buf, size_t nbytes, voi
     hipStream_t st = (hipStream_t)stream;
     const uint4 *body = static_cast<const uint4 *>(buf);
     auto *out = reinterpret_cast<unsigned long long *>(sink);
+    hipEvent_t e0 = (hipEvent_t)start_event, e1 = (hipEvent_t)stop_event;
     if (wpb == 2)
-        hipLaunchKernelGGL(read_roofline_kernel<2>, dim3(blocks), dim3(128), 0, st, body, n_tiles, out);
+        hipExtLaunchKernelGGL(read_roofline_kernel<2>, dim3(blocks), dim3(128), 0, st, e0, e1, 0, body, n_tiles, out);
     else if (wpb == 4)
-        hipLaunchKernelGGL(read_roofline_kernel<4>, dim3(blocks), dim3(256), 0, st, body, n_tiles, out);
+        hipExtLaunchKernelGGL(read_roofline_kernel<4>, dim3(blocks), dim3(256), 0, st, e0, e1, 0, body, n_tiles, out);
     else
-        hipLaunchKernelGGL(read_roofline_kernel<8>, dim3(blocks), dim3(512), 0, st, body, n_tiles, out);
+        hipExtLaunchKernelGGL(read_roofline_kernel<8>, dim3(blocks), dim3(512), 0, st, e0, e1, 0, body, n_tiles, out);
     return hipGetLastError() == hipSuccess ? PPC_OK : PPC_EDEVICE;
+}
+
+ppc_status ppc_read_roofline(uint64_t *sink, const void *buf, size_t nbytes, void *stream) {
+    return ppc_read_roofline_timed(sink, buf, nbytes, stream, nullptr, nullptr);
 }
 
 }  // extern "C"

@@ -13,8 +13,10 @@
 // arrival order, so work of several batches overlaps on the device.  Each
 // batch is: tables host->device, clear of its counters, the persistent
 // batched kernel (the same arithmetic as the plain call), counters
-// device->host, an event.  A request's result is identical to what the
-// plain call computes for it alone.
+// device->host -- captured once per stream as a hipGraph, so a batch costs
+// the host one graph launch and one event record -- then an event.  A
+// request's result is identical to what the plain call computes for it
+// alone.
 //
 // Threading: a server object is used from one host thread at a time.
 #include <hip/hip_runtime.h>
@@ -49,14 +51,16 @@ struct Lane {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
-    bool failed = false;  // an enqueue of the batch in flight failed
+    bool failed = false;          // an enqueue of the batch in flight failed
     std::vector<uint32_t> slots;  // slot ids of the batch in flight
-    // one staging buffer per lane: n ArrayInfo then m WorkItem, copied to
-    // the device in one transfer
-    uint8_t *tables_host = nullptr, *tables_dev = nullptr;
-    unsigned long long *counts_dev = nullptr;
-    uint64_t *counts_host = nullptr;
+    // staging buffer: BatchHeader, ArrayInfo[max_batch], WorkItem[item_cap]
+    // (pinned host, copied to stage_dev by the first kernel of the graph)
+    uint8_t *stage_host = nullptr, *stage_dev = nullptr;
+    unsigned long long *counts_dev = nullptr;  // max_batch x 64, kept zero between batches
+    uint64_t *results_host = nullptr;          // max_batch x 64, written by the graph
     uint32_t *cursor_dev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 }  // namespace ppc
@@ -69,6 +73,7 @@ struct ppc_server {
     uint64_t pool_bytes = 0, column_bytes = 0, n_columns = 0;
     ppc_server_cfg cfg{};
     uint32_t item_cap = 0;
+    size_t items_off = 0, stage_bytes = 0;  // staging layout
     std::vector<Slot> slots;
     std::vector<uint32_t> free_slots;
     std::deque<uint32_t> pending;
@@ -87,11 +92,13 @@ void server_free(ppc_server *s) {
     if (!s) return;
     for (auto &l : s->lanes) {
         if (l.stream) (void)hipStreamSynchronize(l.stream);
+        if (l.exec) (void)hipGraphExecDestroy(l.exec);
+        if (l.graph) (void)hipGraphDestroy(l.graph);
         if (l.done) (void)hipEventDestroy(l.done);
         if (l.stream) (void)hipStreamDestroy(l.stream);
-        if (l.tables_host) (void)hipHostFree(l.tables_host);
-        if (l.counts_host) (void)hipHostFree(l.counts_host);
-        if (l.tables_dev) (void)hipFree(l.tables_dev);
+        if (l.stage_host) (void)hipHostFree(l.stage_host);
+        if (l.results_host) (void)hipHostFree(l.results_host);
+        if (l.stage_dev) (void)hipFree(l.stage_dev);
         if (l.counts_dev) (void)hipFree(l.counts_dev);
         if (l.cursor_dev) (void)hipFree(l.cursor_dev);
     }
@@ -118,7 +125,7 @@ void retire(ppc_server *s) {
             r.status = q == hipSuccess ? PPC_OK : PPC_EDEVICE;
             r.t_submit_ns = sl.t_submit;
             r.t_done_ns = t;
-            std::memcpy(r.counts, l.counts_host + i * 64, sl.req.width * sizeof(uint64_t));
+            std::memcpy(r.counts, l.results_host + i * 64, sl.req.width * sizeof(uint64_t));
             std::memset(r.counts + sl.req.width, 0, (64 - sl.req.width) * sizeof(uint64_t));
             s->completed.push_back(r);
             s->inflight_bytes -= sl.req.nbytes;
@@ -146,7 +153,7 @@ void dispatch(ppc_server *s) {
         if (l.busy) continue;
         uint32_t n = 0, n_items = 0;
         items.clear();
-        ArrayInfo *arrays = reinterpret_cast<ArrayInfo *>(l.tables_host);
+        ArrayInfo *arrays = reinterpret_cast<ArrayInfo *>(l.stage_host + sizeof(BatchHeader));
         while (!s->pending.empty() && n < s->cfg.max_batch) {
             const uint32_t id = s->pending.front();
             const ppc_request &rq = s->slots[id].req;
@@ -166,18 +173,11 @@ void dispatch(ppc_server *s) {
             ++n;
         }
         sort_items_lpt(items);
-        const size_t arrays_bytes = (size_t)n * sizeof(ArrayInfo);
-        std::memcpy(l.tables_host + arrays_bytes, items.data(), items.size() * sizeof(WorkItem));
-        const ArrayInfo *arrays_dev = reinterpret_cast<const ArrayInfo *>(l.tables_dev);
-        const WorkItem *items_dev = reinterpret_cast<const WorkItem *>(l.tables_dev + arrays_bytes);
-        hipError_t e = hipMemcpyAsync(l.tables_dev, l.tables_host, arrays_bytes + items.size() * sizeof(WorkItem),
-                                      hipMemcpyHostToDevice, l.stream);
-        if (e == hipSuccess)
-            e = launch_batched(arrays_dev, items_dev, (uint32_t)items.size(), l.cursor_dev, s->cfg.waves, l.stream,
-                               l.counts_dev, (uint64_t)n * 64);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(l.counts_host, l.counts_dev, (size_t)n * 64 * sizeof(uint64_t), hipMemcpyDeviceToHost,
-                               l.stream);
+        std::memcpy(l.stage_host + s->items_off, items.data(), items.size() * sizeof(WorkItem));
+        BatchHeader *h = reinterpret_cast<BatchHeader *>(l.stage_host);
+        h->n_arrays = n;
+        h->n_items = (uint32_t)items.size();
+        hipError_t e = hipGraphLaunch(l.exec, l.stream);
         if (e == hipSuccess) e = hipEventRecord(l.done, l.stream);
         if (e != hipSuccess) {
             l.failed = true;  // retire() reports the batch with status PPC_EDEVICE
@@ -231,7 +231,7 @@ ppc_status ppc_server_create(ppc_server **out, const void *pool, uint64_t pool_b
     ppc_server_cfg c{};
     if (cfg) c = *cfg;
     if (c.reserved != 0) return PPC_EINVAL;
-    if (c.n_streams == 0) c.n_streams = 4;
+    if (c.n_streams == 0) c.n_streams = 3;
     if (c.max_batch == 0) c.max_batch = 1024;
     if (c.max_inflight == 0) c.max_inflight = 16384;
     if (c.tiles_per_item == 0) c.tiles_per_item = 16;
@@ -256,16 +256,27 @@ ppc_status ppc_server_create(ppc_server **out, const void *pool, uint64_t pool_b
     s->free_slots.reserve(c.max_inflight);
     for (uint32_t i = c.max_inflight; i-- > 0;) s->free_slots.push_back(i);
     s->lanes.resize(c.n_streams);
-    const size_t tables_bytes = (size_t)c.max_batch * sizeof(ArrayInfo) + (size_t)s->item_cap * sizeof(WorkItem);
+    s->items_off = sizeof(BatchHeader) + (size_t)c.max_batch * sizeof(ArrayInfo);
+    s->stage_bytes = s->items_off + (size_t)s->item_cap * sizeof(WorkItem);
+    const size_t counts_bytes = (size_t)c.max_batch * 64 * sizeof(uint64_t);
     for (auto &l : s->lanes) {
         bool ok = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&l.done, hipEventDisableTiming) == hipSuccess &&
-                  hipHostMalloc((void **)&l.tables_host, tables_bytes, 0) == hipSuccess &&
-                  hipHostMalloc((void **)&l.counts_host, (size_t)c.max_batch * 64 * sizeof(uint64_t), 0) ==
-                      hipSuccess &&
-                  hipMalloc(&l.tables_dev, tables_bytes) == hipSuccess &&
-                  hipMalloc(&l.counts_dev, (size_t)c.max_batch * 64 * sizeof(uint64_t)) == hipSuccess &&
+                  // coherent (uncached on the device) so every batch sees the
+                  // host's new tables and the host sees the new results
+                  hipHostMalloc((void **)&l.stage_host, s->stage_bytes, hipHostMallocCoherent) == hipSuccess &&
+                  hipHostMalloc((void **)&l.results_host, counts_bytes, hipHostMallocCoherent) == hipSuccess &&
+                  hipMalloc(&l.stage_dev, s->stage_bytes) == hipSuccess &&
+                  hipMalloc(&l.counts_dev, counts_bytes) == hipSuccess &&
                   hipMalloc(&l.cursor_dev, sizeof(uint32_t)) == hipSuccess;
+        // counters and cursor start at zero; the graph's last kernel leaves
+        // them at zero after every batch
+        ok = ok && hipMemset(l.counts_dev, 0, counts_bytes) == hipSuccess &&
+             hipMemset(l.cursor_dev, 0, sizeof(uint32_t)) == hipSuccess &&
+             hipDeviceSynchronize() == hipSuccess;
+        if (ok) std::memset(l.stage_host, 0, sizeof(BatchHeader));
+        ok = ok && capture_served_graph(&l.graph, &l.exec, l.stage_host, l.stage_dev, s->items_off, s->stage_bytes,
+                                        l.counts_dev, l.results_host, l.cursor_dev, c.waves) == hipSuccess;
         if (!ok) {
             server_free(s);
             return PPC_ENOMEM;

@@ -217,3 +217,28 @@ def test_read_roofline_sums_words(geometry):
     torch.cuda.synchronize()
     want = int(host.view("<u8").sum(dtype=np.uint64))
     assert int(sink.cpu().numpy().view(np.uint64)[0]) == want
+
+
+def test_timed_entry_points_record_the_kernel(geometry):
+    ppc = geometry
+    host = synth.random_bytes((48 << 20) + 9, seed=13)
+    buf = torch.from_numpy(host).to(dev())
+    for w in (8, 64):
+        counts = torch.zeros(w, dtype=torch.int64, device=dev())
+        a, b = ppc.HipEvent(), ppc.HipEvent()
+        ppc.ppc_pospopcnt_timed(w, counts, buf[1:], start_event=a, stop_event=b)
+        torch.cuda.synchronize()
+        assert np.array_equal(ppc.counts_to_numpy(counts), oracle.pospopcnt_mt(host[1:], w, HOST_THREADS))
+        assert 0.0 < a.elapsed_ms(b) < 1000.0
+    sink = torch.zeros(1, dtype=torch.int64, device=dev())
+    a, b = ppc.HipEvent(), ppc.HipEvent()
+    ppc.ppc_read_roofline_timed(sink, buf[:48 << 20], start_event=a, stop_event=b)
+    torch.cuda.synchronize()
+    assert int(sink.cpu().numpy().view(np.uint64)[0]) == int(host[:48 << 20].view("<u8").sum(dtype=np.uint64))
+    assert 0.0 < a.elapsed_ms(b) < 1000.0
+    # no events at all, and nothing launched for an empty input
+    counts = torch.zeros(16, dtype=torch.int64, device=dev())
+    ppc.ppc_pospopcnt_timed(16, counts, buf[:0])
+    ppc.ppc_pospopcnt_timed(16, counts, buf[:100])
+    torch.cuda.synchronize()
+    assert np.array_equal(ppc.counts_to_numpy(counts), oracle.pospopcnt(host[:100], 16))
