@@ -288,8 +288,8 @@ def main():
                     help="time the three accumulation schedules (ppc_pospopcnt_variant 0/1/2) on "
                          "256 MiB at w = 16 and exit (short: also the command to profile them)")
     ap.add_argument("--profile", action="store_true",
-                    help="short fixed run for rocprofv3: 3 plain calls per width, 3 read-roofline "
-                         "calls and 3 plain 256 MiB device copies (counter calibration)")
+                    help="run for rocprofv3: the plain loop (warm-up + steps), the read roofline as "
+                         "often, and 3 plain 256 MiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -327,12 +327,15 @@ def main():
     log("inputs resident: 4 x 256 MiB")
 
     if args.profile:
+        # the bench's own plain loop (warm-up steps, then `steps` steps of one
+        # call per width), then the read roofline the same number of times,
+        # then three plain 256 MiB device copies (counter calibration)
         sink = torch.zeros(1, dtype=torch.int64, device=dev)
         dst = torch.empty(CALL_BYTES, dtype=torch.uint8, device=dev)
-        for i in range(3):
+        for i in range(args.warmup + args.steps):
             for j, w in enumerate(WIDTHS):
                 ppc.ppc_pospopcnt(w, counts[w], bufs[(i + j) % 4])
-        for i in range(3):
+        for i in range(args.warmup + args.steps):
             ppc.ppc_read_roofline(sink, bufs[i % 4])
         for i in range(3):
             dst.copy_(bufs[i % 4])
