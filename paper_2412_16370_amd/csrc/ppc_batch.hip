@@ -59,63 +59,75 @@ __device__ __forceinline__ void fold_and_add(uint32_t acc, uint32_t width, uint3
     if (lane < width && v != 0u) atomicAdd(counts + fold_position(lane, width, m), (unsigned long long)v);
 }
 
-// The persistent loop of one wave: take items from the cursor until it
-// passes n_items.
-__device__ __forceinline__ void run_items(const ArrayInfo *__restrict__ arrays, const WorkItem *__restrict__ items,
-                                          uint32_t n_items, uint32_t *cursor) {
+__device__ __forceinline__ void run_item(const ArrayInfo *__restrict__ arrays, const WorkItem &it) {
     const uint32_t lane = __lane_id();
-    uint32_t ticket = 0;
-    if (lane == 0) ticket = atomicAdd(cursor, 1u);
-    uint32_t cur = (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
-    while (cur < n_items) {
-        // take the next ticket now; its latency hides behind this item
-        uint32_t next = 0;
-        if (lane == 0) next = atomicAdd(cursor, 1u);
-        const WorkItem it = items[cur];
-        const ArrayInfo ai = arrays[it.array];
-        const bool has_edge = (it.flags & 1u) != 0u;
-        uint4 edge = zero4();
-        if (has_edge) {
-            if (lane < 32) {
-                if (lane < ai.edge0_len) edge = byte_as_chunk((uint64_t)(ai.edge0 + lane), ai.edge0[lane]);
-            } else if (lane - 32 < ai.edge1_len) {
-                edge = byte_as_chunk((uint64_t)(ai.edge1 + (lane - 32)), ai.edge1[lane - 32]);
-            }
+    const ArrayInfo ai = arrays[it.array];
+    const bool has_edge = (it.flags & 1u) != 0u;
+    uint4 edge = zero4();
+    if (has_edge) {
+        if (lane < 32) {
+            if (lane < ai.edge0_len) edge = byte_as_chunk((uint64_t)(ai.edge0 + lane), ai.edge0[lane]);
+        } else if (lane - 32 < ai.edge1_len) {
+            edge = byte_as_chunk((uint64_t)(ai.edge1 + (lane - 32)), ai.edge1[lane - 32]);
         }
-        const uint32_t acc =
-            wave_count_tiles<true>(ai.body, ai.n_chunks, ai.n_full, it.tile0, it.tile1, 1u, edge, has_edge);
-        fold_and_add(acc, ai.width, ai.m, ai.counts);
-        cur = (uint32_t)__builtin_amdgcn_readfirstlane((int)next);
+    }
+    const uint32_t acc =
+        wave_count_tiles<true>(ai.body, ai.n_chunks, ai.n_full, it.tile0, it.tile1, 1u, edge, has_edge);
+    fold_and_add(acc, ai.width, ai.m, ai.counts);
+}
+
+// The persistent loop of one wave (index gw of nw): group gw first, then
+// groups nw + ticket while the cursor hands out tickets below the end.  The
+// next ticket is requested before the current group runs, so its latency
+// hides behind the group's work; a wave's first group needs no ticket, so
+// the launch does not start with every wave queueing on one atomic.
+__device__ __forceinline__ void run_groups(const ArrayInfo *__restrict__ arrays, const WorkItem *__restrict__ items,
+                                           const uint32_t *__restrict__ groups, uint32_t n_groups, uint32_t *cursor,
+                                           uint32_t gw, uint32_t nw) {
+    const uint32_t lane = __lane_id();
+    uint32_t grp = gw;
+    while (grp < n_groups) {
+        uint32_t ticket = 0;
+        if (lane == 0) ticket = atomicAdd(cursor, 1u);
+        const uint32_t i0 = groups[grp], i1 = groups[grp + 1];
+        for (uint32_t i = i0; i < i1; ++i) run_item(arrays, items[i]);
+        grp = nw + (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
     }
 }
 
 template <int WPB>
 __global__ __launch_bounds__(WPB *kWave) void batched_kernel(const ArrayInfo *__restrict__ arrays,
-                                                             const WorkItem *__restrict__ items, uint32_t n_items,
+                                                             const WorkItem *__restrict__ items,
+                                                             const uint32_t *__restrict__ groups, uint32_t n_groups,
                                                              uint32_t *cursor) {
-    run_items(arrays, items, n_items, cursor);
+    run_groups(arrays, items, groups, n_groups, cursor, blockIdx.x * WPB + wave_in_block(), gridDim.x * WPB);
 }
 
 // ---- server batch sequence (captured once per stream) ---------------------
-__global__ void stage_copy_kernel(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, uint32_t items_off) {
+__global__ void stage_copy_kernel(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, uint32_t items_off,
+                                  uint32_t groups_off) {
     const BatchHeader h = *reinterpret_cast<const BatchHeader *>(src);
-    const uint32_t n16_arrays = (uint32_t)((sizeof(BatchHeader) + (size_t)h.n_arrays * sizeof(ArrayInfo)) / 16u);
-    const uint32_t n16_items = (uint32_t)((size_t)h.n_items * sizeof(WorkItem) / 16u);
-    const uint4 *s4 = reinterpret_cast<const uint4 *>(src);
-    uint4 *d4 = reinterpret_cast<uint4 *>(dst);
-    const uint32_t off16 = items_off / 16u;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n16_arrays + n16_items; i += gridDim.x * blockDim.x) {
-        const uint32_t j = i < n16_arrays ? i : off16 + (i - n16_arrays);
+    const uint32_t n4_head = (uint32_t)((sizeof(BatchHeader) + (size_t)h.n_arrays * sizeof(ArrayInfo)) / 4u);
+    const uint32_t n4_items = (uint32_t)((size_t)h.n_items * sizeof(WorkItem) / 4u);
+    const uint32_t n4_groups = h.n_groups + 1u;
+    const uint32_t *s4 = reinterpret_cast<const uint32_t *>(src);
+    uint32_t *d4 = reinterpret_cast<uint32_t *>(dst);
+    const uint32_t io = items_off / 4u, go = groups_off / 4u;
+    const uint32_t total = n4_head + n4_items + n4_groups;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const uint32_t j = i < n4_head ? i : (i < n4_head + n4_items ? io + (i - n4_head) : go + (i - n4_head - n4_items));
         d4[j] = s4[j];
     }
 }
 
 template <int WPB>
 __global__ __launch_bounds__(WPB *kWave) void served_batch_kernel(const uint8_t *__restrict__ stage, uint32_t items_off,
-                                                                  uint32_t *cursor) {
+                                                                  uint32_t groups_off, uint32_t *cursor) {
     const BatchHeader *h = reinterpret_cast<const BatchHeader *>(stage);
-    run_items(reinterpret_cast<const ArrayInfo *>(stage + sizeof(BatchHeader)),
-              reinterpret_cast<const WorkItem *>(stage + items_off), h->n_items, cursor);
+    run_groups(reinterpret_cast<const ArrayInfo *>(stage + sizeof(BatchHeader)),
+               reinterpret_cast<const WorkItem *>(stage + items_off),
+               reinterpret_cast<const uint32_t *>(stage + groups_off), h->n_groups, cursor,
+               blockIdx.x * WPB + wave_in_block(), gridDim.x * WPB);
 }
 
 __global__ void served_epilogue_kernel(const uint8_t *__restrict__ stage, unsigned long long *counts,
@@ -129,19 +141,19 @@ __global__ void served_epilogue_kernel(const uint8_t *__restrict__ stage, unsign
 }
 
 hipError_t capture_served_graph(hipGraph_t *graph, hipGraphExec_t *exec, const uint8_t *stage_host,
-                                uint8_t *stage_dev, size_t items_off, size_t stage_bytes,
+                                uint8_t *stage_dev, size_t items_off, size_t groups_off,
                                 unsigned long long *counts_dev, uint64_t *results_host, uint32_t *cursor_dev,
                                 uint32_t waves) {
-    (void)stage_bytes;
     hipStream_t cap = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e != hipSuccess) return e;
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         constexpr int kWpb = 4;
-        hipLaunchKernelGGL(stage_copy_kernel, dim3(16), dim3(256), 0, cap, stage_host, stage_dev, (uint32_t)items_off);
+        hipLaunchKernelGGL(stage_copy_kernel, dim3(16), dim3(256), 0, cap, stage_host, stage_dev, (uint32_t)items_off,
+                           (uint32_t)groups_off);
         hipLaunchKernelGGL(served_batch_kernel<kWpb>, dim3((waves + kWpb - 1) / kWpb), dim3(kWpb * kWave), 0, cap,
-                           (const uint8_t *)stage_dev, (uint32_t)items_off, cursor_dev);
+                           (const uint8_t *)stage_dev, (uint32_t)items_off, (uint32_t)groups_off, cursor_dev);
         hipLaunchKernelGGL(served_epilogue_kernel, dim3(64), dim3(256), 0, cap, (const uint8_t *)stage_dev,
                            counts_dev, results_host, cursor_dev);
         const hipError_t launched = hipGetLastError();
@@ -202,17 +214,34 @@ void sort_items_lpt(std::vector<WorkItem> &items) {
     });
 }
 
-hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, uint32_t n_items,
-                          uint32_t *cursor_dev, uint32_t waves, hipStream_t st, unsigned long long *clear,
-                          uint64_t n_clear) {
+std::vector<uint32_t> build_groups(const std::vector<WorkItem> &items) {
+    std::vector<uint32_t> starts;
+    starts.reserve(items.size() / 4 + 2);
+    uint32_t cost = 0, count = 0;
+    for (uint32_t i = 0; i < (uint32_t)items.size(); ++i) {
+        if (count == 0) starts.push_back(i);
+        cost += (items[i].tile1 - items[i].tile0) + 1u;
+        ++count;
+        if (cost >= kGroupCost || count >= kGroupMax) {
+            cost = 0;
+            count = 0;
+        }
+    }
+    starts.push_back((uint32_t)items.size());
+    return starts;
+}
+
+hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, const uint32_t *groups_dev,
+                          uint32_t n_groups, uint32_t *cursor_dev, uint32_t waves, hipStream_t st,
+                          unsigned long long *clear, uint64_t n_clear) {
     const uint64_t pblocks = std::max<uint64_t>(1, std::min<uint64_t>((n_clear + 255) / 256, 256));
     hipLaunchKernelGGL(prologue_kernel, dim3((unsigned)pblocks), dim3(256), 0, st, cursor_dev, clear, n_clear);
-    if (n_items == 0) return hipGetLastError();
+    if (n_groups == 0) return hipGetLastError();
     constexpr int kWpb = 4;
-    const uint32_t w = std::max<uint32_t>(kWpb, std::min<uint32_t>(waves, n_items + kWpb - 1));
+    const uint32_t w = std::max<uint32_t>(kWpb, std::min<uint32_t>(waves, n_groups + kWpb - 1));
     const uint32_t blocks = (w + kWpb - 1) / kWpb;
-    hipLaunchKernelGGL(batched_kernel<kWpb>, dim3(blocks), dim3(kWpb * kWave), 0, st, arrays_dev, items_dev, n_items,
-                       cursor_dev);
+    hipLaunchKernelGGL(batched_kernel<kWpb>, dim3(blocks), dim3(kWpb * kWave), 0, st, arrays_dev, items_dev,
+                       groups_dev, n_groups, cursor_dev);
     return hipGetLastError();
 }
 
@@ -272,8 +301,9 @@ struct ppc_plan {
     std::vector<ArrayInfo> arrays;
     ArrayInfo *arrays_dev = nullptr;
     WorkItem *items_dev = nullptr;
+    uint32_t *groups_dev = nullptr;
     uint32_t *cursor_dev = nullptr;
-    uint32_t n_items = 0;
+    uint32_t n_items = 0, n_groups = 0;
     uint32_t tiles_per_item = 0;
     uint32_t waves = 0;
     uint64_t total_bytes = 0;
@@ -291,6 +321,7 @@ void plan_free(ppc_plan *p) {
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->arrays_dev) (void)hipFree(p->arrays_dev);
     if (p->items_dev) (void)hipFree(p->items_dev);
+    if (p->groups_dev) (void)hipFree(p->groups_dev);
     if (p->cursor_dev) (void)hipFree(p->cursor_dev);
     delete p;
 }
@@ -308,8 +339,14 @@ std::vector<WorkItem> build_items(const std::vector<ArrayInfo> &arrays, uint32_t
 ppc_status time_candidate(const ArrayInfo *tune_arrays_dev, const std::vector<ArrayInfo> &arrays, uint32_t p,
                           uint32_t waves, uint32_t *cursor_dev, hipStream_t st, int reps, float &ms_out) {
     std::vector<WorkItem> items = build_items(arrays, p);
+    std::vector<uint32_t> groups = build_groups(items);
     WorkItem *items_dev = nullptr;
+    uint32_t *groups_dev = nullptr;
     if (!items.empty() && hipMalloc(&items_dev, items.size() * sizeof(WorkItem)) != hipSuccess) return PPC_ENOMEM;
+    if (hipMalloc(&groups_dev, groups.size() * sizeof(uint32_t)) != hipSuccess) {
+        if (items_dev) (void)hipFree(items_dev);
+        return PPC_ENOMEM;
+    }
     ppc_status rc = PPC_OK;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     std::vector<float> t;
@@ -318,9 +355,14 @@ ppc_status time_candidate(const ArrayInfo *tune_arrays_dev, const std::vector<Ar
         hipMemcpyAsync(items_dev, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice, st) !=
             hipSuccess)
         rc = PPC_EDEVICE;
+    if (rc == PPC_OK &&
+        hipMemcpyAsync(groups_dev, groups.data(), groups.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+        rc = PPC_EDEVICE;
+    const uint32_t n_groups = (uint32_t)groups.size() - 1u;
     for (int r = 0; rc == PPC_OK && r <= reps; ++r) {  // run 0 warms up
         if (hipEventRecord(e0, st) != hipSuccess ||
-            launch_batched(tune_arrays_dev, items_dev, (uint32_t)items.size(), cursor_dev, waves, st) != hipSuccess ||
+            launch_batched(tune_arrays_dev, items_dev, groups_dev, n_groups, cursor_dev, waves, st) != hipSuccess ||
             hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
             rc = PPC_EDEVICE;
             break;
@@ -331,7 +373,9 @@ ppc_status time_candidate(const ArrayInfo *tune_arrays_dev, const std::vector<Ar
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(st);
     if (items_dev) (void)hipFree(items_dev);
+    (void)hipFree(groups_dev);
     if (rc == PPC_OK) {
         std::sort(t.begin(), t.end());
         ms_out = t[t.size() / 2];
@@ -454,9 +498,12 @@ ppc_status ppc_plan_create(ppc_plan **out, const ppc_desc *descs, size_t n, cons
     p->tiles_per_item = std::min(tp, kMaxItemTiles);
     p->waves = wv;
     std::vector<WorkItem> items = build_items(p->arrays, p->tiles_per_item);
+    std::vector<uint32_t> groups = build_groups(items);
     p->n_items = (uint32_t)items.size();
+    p->n_groups = (uint32_t)groups.size() - 1u;
     if ((n > 0 && hipMalloc(&p->arrays_dev, n * sizeof(ArrayInfo)) != hipSuccess) ||
-        (!items.empty() && hipMalloc(&p->items_dev, items.size() * sizeof(WorkItem)) != hipSuccess)) {
+        (!items.empty() && hipMalloc(&p->items_dev, items.size() * sizeof(WorkItem)) != hipSuccess) ||
+        hipMalloc(&p->groups_dev, groups.size() * sizeof(uint32_t)) != hipSuccess) {
         plan_free(p);
         return PPC_ENOMEM;
     }
@@ -464,6 +511,8 @@ ppc_status ppc_plan_create(ppc_plan **out, const ppc_desc *descs, size_t n, cons
                                  st) != hipSuccess) ||
         (!items.empty() && hipMemcpyAsync(p->items_dev, items.data(), items.size() * sizeof(WorkItem),
                                           hipMemcpyHostToDevice, st) != hipSuccess) ||
+        hipMemcpyAsync(p->groups_dev, groups.data(), groups.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess) {
         plan_free(p);
         return PPC_EDEVICE;
@@ -475,7 +524,8 @@ ppc_status ppc_plan_create(ppc_plan **out, const ppc_desc *descs, size_t n, cons
         ok = ok && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
             const bool launched =
-                launch_batched(p->arrays_dev, p->items_dev, p->n_items, p->cursor_dev, p->waves, cap) == hipSuccess;
+                launch_batched(p->arrays_dev, p->items_dev, p->groups_dev, p->n_groups, p->cursor_dev, p->waves, cap) ==
+                hipSuccess;
             ok = hipStreamEndCapture(cap, &p->graph) == hipSuccess && launched;
         }
         ok = ok && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
@@ -493,7 +543,8 @@ ppc_status ppc_plan_run(ppc_plan *p, void *stream) {
     if (!p) return PPC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     if (p->use_graph) return hipGraphLaunch(p->exec, st) == hipSuccess ? PPC_OK : PPC_EDEVICE;
-    return launch_batched(p->arrays_dev, p->items_dev, p->n_items, p->cursor_dev, p->waves, st) == hipSuccess
+    return launch_batched(p->arrays_dev, p->items_dev, p->groups_dev, p->n_groups, p->cursor_dev, p->waves, st) ==
+                   hipSuccess
                ? PPC_OK
                : PPC_EDEVICE;
 }

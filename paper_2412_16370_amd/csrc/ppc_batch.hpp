@@ -36,8 +36,8 @@ static_assert(sizeof(WorkItem) == 16, "WorkItem layout");
 // Header of a server batch in its staging buffer (64 bytes): the
 // ArrayInfo table follows at byte 64, the WorkItem table at a fixed offset.
 struct BatchHeader {
-    uint32_t n_arrays, n_items;
-    uint32_t reserved[14];
+    uint32_t n_arrays, n_items, n_groups;
+    uint32_t reserved[13];
 };
 static_assert(sizeof(BatchHeader) == 64, "BatchHeader layout");
 
@@ -54,10 +54,20 @@ void append_items(std::vector<WorkItem> &items, const ArrayInfo &ai, uint32_t id
 // Sorts items largest first (longest-processing-time order).
 void sort_items_lpt(std::vector<WorkItem> &items);
 
+// Groups consecutive items (in LPT order) into units of work handed out by
+// one ticket: a group closes when its cost (tiles + 1 per item for the
+// per-item reduction) reaches kGroupCost or it holds kGroupMax items, so a
+// large item is a group of its own and tiny ones travel together.  Returns
+// the n_groups + 1 start indices.
+constexpr uint32_t kGroupCost = 16;
+constexpr uint32_t kGroupMax = 64;
+std::vector<uint32_t> build_groups(const std::vector<WorkItem> &items);
+
 // Enqueues the prologue (cursor reset, and a clear of n_clear counters at
-// `clear` if given) and the persistent kernel on `st`.
-hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, uint32_t n_items,
-                          uint32_t *cursor_dev, uint32_t waves, hipStream_t st,
+// `clear` if given) and the persistent kernel on `st`.  Wave g of the grid
+// starts with group g; further groups come from the cursor.
+hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, const uint32_t *groups_dev,
+                          uint32_t n_groups, uint32_t *cursor_dev, uint32_t waves, hipStream_t st,
                           unsigned long long *clear = nullptr, uint64_t n_clear = 0);
 
 // Captures the fixed launch sequence of one server stream into a graph:
@@ -67,7 +77,7 @@ hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev
 // the cursor for the next batch.  Per batch the host only fills the staging
 // buffer and launches the graph.
 hipError_t capture_served_graph(hipGraph_t *graph, hipGraphExec_t *exec, const uint8_t *stage_host,
-                                uint8_t *stage_dev, size_t items_off, size_t stage_bytes,
+                                uint8_t *stage_dev, size_t items_off, size_t groups_off,
                                 unsigned long long *counts_dev, uint64_t *results_host, uint32_t *cursor_dev,
                                 uint32_t waves);
 

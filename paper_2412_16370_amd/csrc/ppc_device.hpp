@@ -286,14 +286,36 @@ __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t
                                                      uint32_t t0, uint32_t t_end, uint32_t stride, uint4 edge,
                                                      bool has_edge) {
     const uint32_t lane = __lane_id();
+    const uint32_t full_end = t_end < n_full ? t_end : n_full;
+    // number of whole tiles this wave walks (wave-uniform)
+    const uint32_t n_mine = t0 < full_end ? (full_end - t0 + stride - 1) / stride : 0u;
+    {
+        // Short path (the transpose-then-popcount idea of the paper's future
+        // work): when the wave holds at most one chunk per lane -- no whole
+        // tile, and a partial tile of at most 64 chunks or none -- the
+        // carry-save front end is skipped.  The lane's chunk and its edge
+        // chunk form a 2-plane bit-sliced number (half adder) that goes
+        // straight into the cross-lane transposes and popcounts.
+        const uint32_t t = t0 + n_mine * stride;
+        const bool walks_partial = t < t_end && t == n_full && (uint64_t)n_full * kTileChunks < n_chunks;
+        const uint64_t partial_chunks = walks_partial ? n_chunks - (uint64_t)n_full * kTileChunks : 0u;
+        if (n_mine == 0 && partial_chunks <= (uint64_t)kWave) {
+            if (!walks_partial && !has_edge) return 0u;
+            uint4 v = zero4();
+            if (walks_partial && lane < partial_chunks) v = body[(uint64_t)n_full * kTileChunks + lane];
+            uint4 p[kPlanes];
+#pragma unroll
+            for (int e = 0; e < kPlanes; ++e) p[e] = zero4();
+            p[0] = make_uint4(v.x ^ edge.x, v.y ^ edge.y, v.z ^ edge.z, v.w ^ edge.w);
+            p[1] = make_uint4(v.x & edge.x, v.y & edge.y, v.z & edge.z, v.w & edge.w);
+            return wave_position_counts(p, 2u);
+        }
+    }
     Planes pl;
     pl.clear();
     pl.a1 = edge;
     bool any = has_edge;
     uint32_t acc = 0, seg = 0;
-    const uint32_t full_end = t_end < n_full ? t_end : n_full;
-    // number of whole tiles this wave walks (wave-uniform)
-    const uint32_t n_mine = t0 < full_end ? (full_end - t0 + stride - 1) / stride : 0u;
     auto tile_ptr = [&](uint32_t i) { return body + (uint64_t)(t0 + i * stride) * kTileChunks + lane; };
     auto add_tile = [&](const uint4 (&v)[kLoadsPerTile]) {
         ++seg;

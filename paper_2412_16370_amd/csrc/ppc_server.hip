@@ -73,7 +73,7 @@ struct ppc_server {
     uint64_t pool_bytes = 0, column_bytes = 0, n_columns = 0;
     ppc_server_cfg cfg{};
     uint32_t item_cap = 0;
-    size_t items_off = 0, stage_bytes = 0;  // staging layout
+    size_t items_off = 0, groups_off = 0, stage_bytes = 0;  // staging layout
     std::vector<Slot> slots;
     std::vector<uint32_t> free_slots;
     std::deque<uint32_t> pending;
@@ -173,10 +173,13 @@ void dispatch(ppc_server *s) {
             ++n;
         }
         sort_items_lpt(items);
+        const std::vector<uint32_t> groups = build_groups(items);
         std::memcpy(l.stage_host + s->items_off, items.data(), items.size() * sizeof(WorkItem));
+        std::memcpy(l.stage_host + s->groups_off, groups.data(), groups.size() * sizeof(uint32_t));
         BatchHeader *h = reinterpret_cast<BatchHeader *>(l.stage_host);
         h->n_arrays = n;
         h->n_items = (uint32_t)items.size();
+        h->n_groups = (uint32_t)groups.size() - 1u;
         hipError_t e = hipGraphLaunch(l.exec, l.stream);
         if (e == hipSuccess) e = hipEventRecord(l.done, l.stream);
         if (e != hipSuccess) {
@@ -257,7 +260,8 @@ ppc_status ppc_server_create(ppc_server **out, const void *pool, uint64_t pool_b
     for (uint32_t i = c.max_inflight; i-- > 0;) s->free_slots.push_back(i);
     s->lanes.resize(c.n_streams);
     s->items_off = sizeof(BatchHeader) + (size_t)c.max_batch * sizeof(ArrayInfo);
-    s->stage_bytes = s->items_off + (size_t)s->item_cap * sizeof(WorkItem);
+    s->groups_off = s->items_off + (size_t)s->item_cap * sizeof(WorkItem);
+    s->stage_bytes = s->groups_off + ((size_t)s->item_cap + 1) * sizeof(uint32_t);
     const size_t counts_bytes = (size_t)c.max_batch * 64 * sizeof(uint64_t);
     for (auto &l : s->lanes) {
         bool ok = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) == hipSuccess &&
@@ -275,7 +279,7 @@ ppc_status ppc_server_create(ppc_server **out, const void *pool, uint64_t pool_b
              hipMemset(l.cursor_dev, 0, sizeof(uint32_t)) == hipSuccess &&
              hipDeviceSynchronize() == hipSuccess;
         if (ok) std::memset(l.stage_host, 0, sizeof(BatchHeader));
-        ok = ok && capture_served_graph(&l.graph, &l.exec, l.stage_host, l.stage_dev, s->items_off, s->stage_bytes,
+        ok = ok && capture_served_graph(&l.graph, &l.exec, l.stage_host, l.stage_dev, s->items_off, s->groups_off,
                                         l.counts_dev, l.results_host, l.cursor_dev, c.waves) == hipSuccess;
         if (!ok) {
             server_free(s);
