@@ -231,11 +231,11 @@ def size_sweep(ppc, torch, synth, dev, out_path):
     """Speed by array length (the paper's main experiment, Section 5.3) on
     the GPU: for each size, calls are repeated on the same buffer and the
     same counters (loop-carried, as in Section 5.1) until at least 20 ms
-    and 10 calls; the median call time gives GB/s."""
+    and 10 calls; the median kernel time (events recorded by the dispatch)
+    gives GB/s, and the wall time per back-to-back call is recorded too."""
     sizes = sorted([1 << i for i in range(1, 31)] + [3 << i for i in range(0, 30)])
     buf = synth.device_bernoulli(sizes[-1], 0.5, seed=60, device=dev)
     sink = torch.zeros(1, dtype=torch.int64, device=dev)
-    stream = torch.cuda.current_stream()
     os.makedirs(os.path.dirname(out_path), exist_ok=True)
     with open(out_path, "w") as out:
         for n in sizes:
@@ -243,29 +243,35 @@ def size_sweep(ppc, torch, synth, dev, out_path):
             for w in WIDTHS + (0,):
                 counts = torch.zeros(max(w, 1), dtype=torch.int64, device=dev)
                 if w:
-                    call = lambda: ppc.ppc_pospopcnt(w, counts, buf[:n])
+                    call = lambda a, b: ppc.ppc_pospopcnt_timed(w, counts, buf[:n], start_event=a, stop_event=b)
                 else:
                     if n % 16384:
                         continue
-                    call = lambda: ppc.ppc_read_roofline(sink, buf[:n])
+                    call = lambda a, b: ppc.ppc_read_roofline_timed(sink, buf[:n], start_event=a, stop_event=b)
                 for _ in range(3):
-                    call()
+                    call(None, None)
+                # calls back to back on one stream, each kernel timed by its
+                # own dispatch (the loop-carried reuse of buffer and counters
+                # of Section 5.1); at least 10 calls and 20 ms of kernel time
                 times = []
                 t_total = 0.0
                 while len(times) < 10 or t_total < 20.0:
-                    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                    a.record(stream)
-                    call()
-                    b.record(stream)
-                    b.synchronize()
-                    times.append(a.elapsed_time(b))
-                    t_total += times[-1]
+                    evs = [(ppc.HipEvent(), ppc.HipEvent()) for _ in range(10)]
+                    t0 = time.perf_counter()
+                    for a, b in evs:
+                        call(a, b)
+                    torch.cuda.synchronize()
+                    wall = (time.perf_counter() - t0) / len(evs)
+                    for a, b in evs:
+                        times.append(a.elapsed_ms(b))
+                        t_total += times[-1]
                     if len(times) >= 2000:
                         break
                 med = sorted(times)[len(times) // 2]
                 key = ("w%d" % w) if w else "read_roofline"
                 row[key + "_us"] = round(med * 1e3, 3)
                 row[key + "_GBps"] = round(n / (med * 1e-3) / 1e9, 3)
+                row[key + "_wall_us_per_call"] = round(wall * 1e6, 3)
             out.write(json.dumps(row) + "\n")
             out.flush()
             log("sweep %11d B: w16 %9.2f us %9.1f GB/s" % (n, row["w16_us"], row["w16_GBps"]))
