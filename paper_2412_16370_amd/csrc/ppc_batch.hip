@@ -44,21 +44,6 @@ __global__ void prologue_kernel(uint32_t *cursor, unsigned long long *clear, uin
         clear[i] = 0ull;
 }
 
-// Fold of a wave's 64 address-position counts (lane L) into w counters
-// relative to the array's pointer, then at most w atomics.  Lanes L and
-// L' feed the same output when they differ only in address-slot bits that
-// the width ignores: those are summed with cross-lane shuffles first.
-__device__ __forceinline__ void fold_and_add(uint32_t acc, uint32_t width, uint32_t m,
-                                             unsigned long long *counts) {
-    const uint32_t lane = __lane_id();
-    const uint32_t s = width >> 3;
-    uint64_t v = acc;
-    if (s <= 4u) v += __shfl_xor(v, 32);
-    if (s <= 2u) v += __shfl_xor(v, 16);
-    if (s == 1u) v += __shfl_xor(v, 8);
-    if (lane < width && v != 0u) atomicAdd(counts + fold_position(lane, width, m), (unsigned long long)v);
-}
-
 __device__ __forceinline__ void run_item(const ArrayInfo *__restrict__ arrays, const WorkItem &it) {
     const uint32_t lane = __lane_id();
     const ArrayInfo ai = arrays[it.array];
@@ -73,7 +58,7 @@ __device__ __forceinline__ void run_item(const ArrayInfo *__restrict__ arrays, c
     }
     const uint32_t acc =
         wave_count_tiles<true>(ai.body, ai.n_chunks, ai.n_full, it.tile0, it.tile1, 1u, edge, has_edge);
-    fold_and_add(acc, ai.width, ai.m, ai.counts);
+    fold_add(acc, ai.width, ai.m, ai.counts);
 }
 
 // The persistent loop of one wave (index gw of nw): group gw first, then

@@ -147,28 +147,29 @@ __device__ __forceinline__ uint32_t partner_xor(uint32_t x) {
     }
 }
 
-// One stage of a 32x32 bit-matrix transpose across the lanes of each 32-lane
-// half (the recursive block transpose of Section 4.5, done across lanes
-// instead of inside one register).  Row = lane, column = bit.  The rows with
-// (row & S) == 0 trade their columns with (col & S) != 0 for the partner's
-// columns with (col & S) == 0.
-template <int S>
-__device__ __forceinline__ uint32_t transpose_stage(uint32_t x, uint32_t take_mask, uint32_t rot) {
-    uint32_t partner = partner_xor<S>(x);
-    uint32_t t = __builtin_amdgcn_alignbit(partner, partner, rot);  // rotate right
-    return (take_mask & t) | (~take_mask & x);
-}
-
-// Per-lane constants of transpose_stage<S>.
+// 32x32 bit-matrix transpose across the lanes of each 32-lane half (the
+// recursive block transpose of Section 4.5, done across lanes instead of
+// inside one register).  Row = lane, column = bit.  Stage S trades, between
+// rows r and r ^ S, the bits whose column has bit S different from the row's
+// bit S; the five stages commute and after all of them lane r holds column
+// r.  Stages 16 and 8 move whole bytes, so one byte permute (v_perm_b32)
+// merges the partner's bytes; stages 4, 2 and 1 rotate the partner's word
+// and merge it by a bit mask.
 struct TransposeConsts {
-    uint32_t take[5], rot[5];
+    uint32_t sel16, sel8;  // v_perm_b32 selectors: bytes 0-3 = own word, 4-7 = partner's
+    uint32_t take[3], rot[3];  // stages 4, 2, 1
     __device__ __forceinline__ TransposeConsts() {
         const uint32_t lane = lane_id();
-        const uint32_t low_mask[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u,
-                                      0x55555555u};
-        const uint32_t shift[5] = {16, 8, 4, 2, 1};
+        // row bit 4 clear: keep own bytes 0,1, take partner's bytes 0,1 as 2,3;
+        // set: take partner's bytes 2,3 as 0,1, keep own bytes 2,3
+        sel16 = (lane & 16u) ? 0x03020706u : 0x05040100u;
+        // row bit 3 clear: own bytes 0,2 stay, partner's bytes 0,2 go to 1,3;
+        // set: partner's bytes 1,3 go to 0,2, own bytes 1,3 stay
+        sel8 = (lane & 8u) ? 0x03070105u : 0x06020400u;
+        const uint32_t low_mask[3] = {0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+        const uint32_t shift[3] = {4, 2, 1};
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
+        for (int i = 0; i < 3; ++i) {
             const bool upper = (lane & shift[i]) != 0;
             take[i] = upper ? low_mask[i] : ~low_mask[i];
             rot[i] = upper ? shift[i] : 32u - shift[i];
@@ -176,73 +177,105 @@ struct TransposeConsts {
     }
 };
 
-// After the transpose lane r (inside each half) holds column r of the
-// 32x32 matrix; its popcount is the number of rows with that bit set.
-__device__ __forceinline__ uint32_t column_popcount(uint32_t x, const TransposeConsts &tc) {
-    x = transpose_stage<16>(x, tc.take[0], tc.rot[0]);
-    x = transpose_stage<8>(x, tc.take[1], tc.rot[1]);
-    x = transpose_stage<4>(x, tc.take[2], tc.rot[2]);
-    x = transpose_stage<2>(x, tc.take[3], tc.rot[3]);
-    x = transpose_stage<1>(x, tc.take[4], tc.rot[4]);
-    return __builtin_popcount(x);
+// Merge step of the bit-granular stages: the partner's word rotated so that
+// its traded bits land on the own word's traded positions.
+__device__ __forceinline__ uint32_t merge_rotated(uint32_t own, uint32_t partner, uint32_t take, uint32_t rot) {
+    const uint32_t t = __builtin_amdgcn_alignbit(partner, partner, rot);  // rotate right
+    return (take & t) | (~take & own);
+}
+
+// Transposes NZ planes stage by stage (every plane's partner fetches of a
+// stage are issued before any of them is consumed, so the LDS swizzles of
+// the xor-16 and xor-4 stages overlap and DPP reads never wait on the
+// previous instruction), then returns in lane r (inside each half) the sum
+// over planes of popcount(column r of plane e) << e.
+template <int NZ>
+__device__ __forceinline__ uint32_t transpose_popcount(uint32_t (&z)[NZ], const TransposeConsts &tc) {
+    uint32_t t[NZ];
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) t[e] = swz_xor<16>(z[e]);
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) z[e] = __builtin_amdgcn_perm(t[e], z[e], tc.sel16);
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) t[e] = partner_xor<8>(z[e]);
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) z[e] = __builtin_amdgcn_perm(t[e], z[e], tc.sel8);
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) t[e] = swz_xor<4>(z[e]);
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) z[e] = merge_rotated(z[e], t[e], tc.take[0], tc.rot[0]);
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) t[e] = partner_xor<2>(z[e]);
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) z[e] = merge_rotated(z[e], t[e], tc.take[1], tc.rot[1]);
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) t[e] = partner_xor<1>(z[e]);
+#pragma unroll
+    for (int e = 0; e < NZ; ++e) z[e] = merge_rotated(z[e], t[e], tc.take[2], tc.rot[2]);
+    uint32_t total = 0;
+#pragma unroll
+    for (int e = NZ - 1; e >= 0; --e) total = (total << 1) + (uint32_t)__builtin_popcount(z[e]);
+    return total;
 }
 
 // End-of-segment reduction of a wave's bit planes into 64 integer counts
 // (the final accumulation of Section 4.5, rebuilt for a 64-lane wavefront).
 // Returns, in lane L, the number of set bits at address position L summed
 // over all lanes and planes with their weights.  All 64 lanes must be
-// active.  Plane e has weight 2^e; planes e >= e_used are zero (e_used is
-// wave-uniform) and are skipped.
+// active.  Plane e has weight 2^e; only planes e < NZ - 2 may be nonzero
+// (with e_used nonzero planes, NZ >= e_used + 2 planes hold the result).
 //   step A: inside each lane add dword x to z and y to w (same positions),
 //           as bit-sliced numbers -> planes for positions 0..31 (X) and
 //           32..63 (Y), one plane more;
 //   step B: lanes L < 32 take X from lane L+32, lanes L >= 32 take Y from
 //           lane L-32 (one permlane32 swap per plane), and add -> one plane
 //           more again, one dword per plane;
-//   step C: per plane, a 32x32 cross-lane transpose and a popcount.
-__device__ __forceinline__ uint32_t wave_position_counts(const uint4 (&p)[kPlanes], uint32_t e_used) {
-    uint32_t X[kPlanes + 1], Y[kPlanes + 1];
+//   step C: the planes are transposed across the lanes of each half and
+//           popcounted with their weights.
+template <int NZ>
+__device__ __forceinline__ uint32_t reduce_planes(const uint4 (&p)[kPlanes]) {
+    static_assert(NZ >= 3 && NZ <= kPlanes + 2, "plane count");
+    uint32_t X[NZ - 1], Y[NZ - 1];
     {
         uint32_t cx = 0, cy = 0;
 #pragma unroll
-        for (int e = 0; e < kPlanes; ++e) {
-            X[e] = parity3(p[e].x, p[e].z, cx);
-            Y[e] = parity3(p[e].y, p[e].w, cy);
-            const uint32_t ncx = majority3(p[e].x, p[e].z, cx);
-            const uint32_t ncy = majority3(p[e].y, p[e].w, cy);
+        for (int e = 0; e < NZ - 1; ++e) {
+            const uint4 q = e < kPlanes ? p[e] : zero4();
+            X[e] = parity3(q.x, q.z, cx);
+            Y[e] = parity3(q.y, q.w, cy);
+            const uint32_t ncx = majority3(q.x, q.z, cx);
+            const uint32_t ncy = majority3(q.y, q.w, cy);
             cx = ncx;
             cy = ncy;
         }
-        X[kPlanes] = cx;
-        Y[kPlanes] = cy;
+        // cx, cy are zero here: the sums fit in NZ - 1 planes
     }
-    uint32_t Z[kPlanes + 2];
+    uint32_t Z[NZ];
     {
         uint32_t c = 0;
 #pragma unroll
-        for (int e = 0; e <= kPlanes; ++e) {
-            if ((uint32_t)e <= e_used) {
-                // after the swap: lo = X (lanes < 32) / Y of lane-32 (lanes >= 32),
-                //                 hi = X of lane+32 (lanes < 32) / Y (lanes >= 32)
-                const auto sw = __builtin_amdgcn_permlane32_swap(X[e], Y[e], false, false);
-                const uint32_t lo = sw[0], hi = sw[1];
-                Z[e] = parity3(lo, hi, c);
-                c = majority3(lo, hi, c);
-            } else if ((uint32_t)e == e_used + 1u) {
-                Z[e] = c;  // the carry out of the top used plane
-                c = 0;
-            } else {
-                Z[e] = 0;
-            }
+        for (int e = 0; e < NZ - 1; ++e) {
+            // after the swap: lo = X (lanes < 32) / Y of lane-32 (lanes >= 32),
+            //                 hi = X of lane+32 (lanes < 32) / Y (lanes >= 32)
+            const auto sw = __builtin_amdgcn_permlane32_swap(X[e], Y[e], false, false);
+            const uint32_t lo = sw[0], hi = sw[1];
+            Z[e] = parity3(lo, hi, c);
+            c = majority3(lo, hi, c);
         }
-        Z[kPlanes + 1] = c;  // nonzero only when every plane is in use
+        Z[NZ - 1] = c;
     }
     const TransposeConsts tc;
-    uint32_t total = 0;
-#pragma unroll
-    for (int e = 0; e < kPlanes + 2; ++e)
-        if ((uint32_t)e < e_used + 2u) total += column_popcount(Z[e], tc) << e;
-    return total;
+    return transpose_popcount<NZ>(Z, tc);
+}
+
+// Dispatch on the number of planes in use (wave-uniform): planes
+// e >= e_used are zero and are not processed.
+__device__ __forceinline__ uint32_t wave_position_counts(const uint4 (&p)[kPlanes], uint32_t e_used) {
+    if (e_used <= 2u) return reduce_planes<4>(p);
+    if (e_used <= 4u) return reduce_planes<6>(p);
+    if (e_used <= 6u) return reduce_planes<8>(p);
+    if (e_used <= 8u) return reduce_planes<10>(p);
+    return reduce_planes<kPlanes + 2>(p);
 }
 
 __device__ __forceinline__ uint32_t planes_position_counts(const Planes &pl, uint32_t b_used) {
@@ -381,6 +414,44 @@ __device__ __forceinline__ uint32_t fold_position(uint32_t P, uint32_t w, uint32
     const uint32_t s = w >> 3;
     const uint32_t a = P >> 3;
     return 8u * ((a + 8u - m) & (s - 1u)) + (P & 7u);
+}
+
+// v + (v of lane ^ S), 64-bit, for all 64 lanes: a permlane32 swap for
+// S = 32, the lane exchanges of partner_xor below that.
+template <int S>
+__device__ __forceinline__ uint64_t add_partner_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    if constexpr (S == 32) {
+        // swap(x, x): element 0 and element 1 are, in some order, the own
+        // value and that of lane ^ 32
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        return (((uint64_t)h[0] << 32) | l[0]) + (((uint64_t)h[1] << 32) | l[1]);
+    } else {
+        const uint32_t plo = partner_xor<S>(lo), phi = partner_xor<S>(hi);
+        return v + (((uint64_t)phi << 32) | plo);
+    }
+}
+
+// Adds a wave's 64 position counts (lane L holds address position L) into
+// the caller's counters: positions that f_w sends to the same counter are
+// summed across lanes first (lane bits 5, 4, 3 select the byte slot), then
+// lanes j < w add one counter each.  Width 0 sums everything into
+// counts[0] (the total popcount).  All 64 lanes must be active.
+__device__ __forceinline__ void fold_add(uint64_t v, uint32_t width, uint32_t m, unsigned long long *counts) {
+    const uint32_t lane = __lane_id();
+    const uint32_t s = width >> 3;
+    if (s <= 4u) v = add_partner_u64<32>(v);
+    if (s <= 2u) v = add_partner_u64<16>(v);
+    if (s <= 1u) v = add_partner_u64<8>(v);
+    if (width == 0u) {
+        v = add_partner_u64<4>(v);
+        v = add_partner_u64<2>(v);
+        v = add_partner_u64<1>(v);
+        if (lane == 0u && v != 0u) atomicAdd(counts, (unsigned long long)v);
+        return;
+    }
+    if (lane < width && v != 0u) atomicAdd(counts + fold_position(lane, width, m), (unsigned long long)v);
 }
 
 }  // namespace ppc

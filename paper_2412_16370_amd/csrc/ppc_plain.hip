@@ -68,25 +68,11 @@ __global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
     __shared__ uint32_t part[WPB][kWave];
     part[wib][lane] = acc;
     __syncthreads();
-    if (a.width == 0) {  // conventional population count: every position into counts[0]
-        if (wib == 0) {
-            uint64_t v = 0;
+    if (wib == 0) {  // block sum per address position, then f_w and the atomics
+        uint64_t v = 0;
 #pragma unroll
-            for (int wv = 0; wv < WPB; ++wv) v += part[wv][lane];
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-            if (lane == 0 && v) atomicAdd(a.counts, (unsigned long long)v);
-        }
-    } else if (threadIdx.x < a.width) {
-        const uint32_t s = a.width >> 3;
-        const uint32_t j = threadIdx.x;
-        const uint32_t k = j & 7u;
-        const uint32_t a0 = ((j >> 3) + a.m) & (s - 1u);
-        unsigned long long sum = 0;
-        for (uint32_t slot = a0; slot < 8u; slot += s)
-#pragma unroll
-            for (int wv = 0; wv < WPB; ++wv) sum += part[wv][8u * slot + k];
-        if (sum) atomicAdd(a.counts + j, sum);
+        for (int wv = 0; wv < WPB; ++wv) v += part[wv][lane];
+        fold_add(v, a.width, a.m, a.counts);
     }
 }
 
@@ -135,17 +121,14 @@ __global__ __launch_bounds__(WPB *kWave) void read_roofline_kernel(const uint4 *
             for (int j = 0; j < kLoadsPerTile; ++j) acc += va[j];
         }
     }
-    uint64_t s = acc.x + acc.y;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
-    __shared__ uint64_t part[WPB];
-    if (lane == 0) part[threadIdx.x / kWave] = s;
+    __shared__ uint64_t part[WPB][kWave];
+    part[wave_in_block()][lane] = acc.x + acc.y;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (wave_in_block() == 0) {
         uint64_t b = 0;
 #pragma unroll
-        for (int wv = 0; wv < WPB; ++wv) b += part[wv];
-        if (b) atomicAdd(sink, (unsigned long long)b);
+        for (int wv = 0; wv < WPB; ++wv) b += part[wv][lane];
+        fold_add(b, 0u, 0u, sink);
     }
 }
 
