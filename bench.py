@@ -115,10 +115,26 @@ def cpu_baseline(seconds_target=15.0):
     t0 = time.perf_counter()
     oracle.pospopcnt(sample[: 16 * MiB], 16)
     st = 16 * MiB / (time.perf_counter() - t0) / 1e9
+    cfg1 = synth.random_bytes(2 * MiB, seed=0)
+    t0 = time.perf_counter()
+    for _ in range(8):
+        oracle.pospopcnt(cfg1, 16)
+    st_cfg1 = 8 * 2 * MiB / (time.perf_counter() - t0) / 1e9
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(mt, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": "%d MiB passes of 64 MiB random bytes over w=8,16,32,64 "
                       "(multithreaded word loop, split at word boundaries)" % (done // MiB),
-            "single_thread_GBps": round(st, 4)}
+            "single_thread_GBps": round(st, 4),
+            "config1_2MiB_w16_single_thread_GBps": round(st_cfg1, 4),
+            "cpu_model": model, "host_cpus_visible": os.cpu_count()}
 
 
 def batched_leg(ppc, torch, synth, dev, reps):
@@ -281,6 +297,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--kernel-seconds", type=float, default=1.0,
+                    help="accumulated kernel time of the event-timed pass (at least --steps steps)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batched", action="store_true")
@@ -367,29 +385,35 @@ def main():
     total_bytes = args.steps * len(WIDTHS) * CALL_BYTES
     value = total_bytes / wall / 1e9
 
-    # kernel timing: the same K steps again, every launch carrying a HIP event
+    # kernel timing: the same rotation again, every launch carrying a HIP event
     # pair that its own dispatch records (kernel start and end on the launch
-    # stream).  Such events leave the queue idle for ~5 us after each kernel,
-    # which is why the whole-job pass above runs without them.
-    ev = [(w, ppc.HipEvent(), ppc.HipEvent()) for i in range(args.steps) for w in WIDTHS]
+    # stream), for at least K steps and `--kernel-seconds` of accumulated
+    # kernel time.  Such events leave the queue idle for ~5 us after each
+    # kernel, which is why the whole-job pass above runs without them.
+    ev = [(ppc.HipEvent(), ppc.HipEvent()) for _ in range(args.steps * len(WIDTHS))]
+    per_call = {w: [] for w in WIDTHS}
+    kernel_s, steps_timed = 0.0, 0
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    k = 0
-    for i in range(args.steps):
-        for j, w in enumerate(WIDTHS):
-            _, a, b = ev[k]
-            ppc.ppc_pospopcnt_timed(w, counts[w], bufs[(i + j) % 4], start_event=a, stop_event=b)
-            k += 1
-    torch.cuda.synchronize()
+    while steps_timed < args.steps or kernel_s < args.kernel_seconds:
+        for i in range(args.steps):
+            for j, w in enumerate(WIDTHS):
+                a, b = ev[i * len(WIDTHS) + j]
+                ppc.ppc_pospopcnt_timed(w, counts[w], bufs[(steps_timed + i + j) % 4], start_event=a, stop_event=b)
+        torch.cuda.synchronize()
+        for i in range(args.steps):
+            for j, w in enumerate(WIDTHS):
+                a, b = ev[i * len(WIDTHS) + j]
+                ms = a.elapsed_ms(b)
+                per_call[w].append(ms)
+                kernel_s += ms * 1e-3
+        steps_timed += args.steps
     wall_timed = time.perf_counter() - t1
-    per_call = {w: [] for w in WIDTHS}
-    for w, a, b in ev:
-        per_call[w].append(a.elapsed_ms(b))
-    all_ms = [x for v in per_call.values() for x in v]
+    all_ms = sorted(x for v in per_call.values() for x in v)
     avg_ms = sum(all_ms) / len(all_ms)
     achieved = CALL_BYTES / (avg_ms * 1e-3) / 1e9
-    log("plain: %.1f GB/s whole-job (%.2f us per call), kernel avg %.2f us -> %.1f GB/s"
-        % (value, wall / (args.steps * len(WIDTHS)) * 1e6, avg_ms * 1e3, achieved))
+    log("plain: %.1f GB/s whole-job (%.2f us per call), kernel avg %.2f us over %d launches -> %.1f GB/s"
+        % (value, wall / (args.steps * len(WIDTHS)) * 1e6, avg_ms * 1e3, len(all_ms), achieved))
 
     # read-only roofline kernel on the same buffers
     sink = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -411,8 +435,39 @@ def main():
         del dbufs
     density["0.5"] = round(CALL_BYTES / (sum(per_call[16]) / len(per_call[16]) * 1e-3) / 1e9, 1)
 
+    def us_stats(v):
+        v = sorted(v)
+        return {"avg": round(sum(v) / len(v) * 1e3, 2), "median": round(v[len(v) // 2] * 1e3, 2),
+                "min": round(v[0] * 1e3, 2), "max": round(v[-1] * 1e3, 2), "launches": len(v)}
+
     per_width = {str(w): round(CALL_BYTES / (sum(v) / len(v) * 1e-3) / 1e9, 1)
                  for w, v in per_call.items()}
+    per_width_us = {str(w): us_stats(v) for w, v in per_call.items()}
+
+    # one GPU's share of a 256 MiB array split over 8 GPUs: 32 MiB slices of
+    # the four buffers, 32 distinct slices in rotation (1 GiB, DRAM-resident)
+    slices = [b[k * 32 * MiB:(k + 1) * 32 * MiB] for b in bufs for k in range(8)]
+    c16 = torch.zeros(16, dtype=torch.int64, device=dev)
+    shard = dispatch_timed(lambda b, e0, e1: ppc.ppc_pospopcnt_timed(16, c16, b, start_event=e0, stop_event=e1),
+                           slices, 4 * len(slices), torch)
+    shard_us = sum(shard) / len(shard) * 1e3
+    del slices
+
+    # config 1: one 2 MiB array of 2^20 uint16 words, random bytes from seed 0
+    small = torch.from_numpy(synth.random_bytes(2 * MiB, seed=0)).to(dev)
+    for _ in range(10):
+        ppc.ppc_pospopcnt(16, c16, small)
+    small_ms = sorted(dispatch_timed(lambda b, e0, e1: ppc.ppc_pospopcnt_timed(16, c16, b, start_event=e0,
+                                                                                 stop_event=e1),
+                                     [small], 200, torch))
+    lib, st = ppc.lib(), torch.cuda.current_stream().cuda_stream
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(500):
+        lib.ppc_pospopcnt(16, c16.data_ptr(), small.data_ptr(), 2 * MiB, st)
+    torch.cuda.synchronize()
+    small_wall_us = (time.perf_counter() - t2) / 500 * 1e6
+    del small
     result = {
         "metric": "pospopcnt GB/s & % HBM peak (256 MiB); batched vs plain; served p50/p99",
         "value": round(value, 1),
@@ -433,13 +488,26 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic_from_profiles()},
         "kernel_avg_us": round(avg_ms * 1e3, 2),
+        "kernel_us": us_stats(all_ms) | {"seconds": round(kernel_s, 3)},
+        "kernel_us_per_width": per_width_us,
         "wall_us_per_call": round(wall / (args.steps * len(WIDTHS)) * 1e6, 2),
         "timing": "value: K steps of plain calls, host clock between synchronisations; "
-                  "roofline.achieved: the same K steps again with dispatch-recorded HIP events "
-                  "on every launch (whole-job rate of that pass: %.1f GB/s)" % (total_bytes / wall_timed / 1e9),
+                  "roofline.achieved: the same rotation again with dispatch-recorded HIP events "
+                  "on every launch, for at least K steps and %.1f s of kernel time (%d launches; whole-job "
+                  "rate of that pass, which synchronises every K steps: %.1f GB/s)"
+                  % (args.kernel_seconds, len(all_ms), steps_timed * len(WIDTHS) * CALL_BYTES / wall_timed / 1e9),
         "per_width_GBps": per_width,
         "density_GBps_w16": density,
         "read_roofline_GBps": round(rl_gbps, 1),
+        "shard_32MiB_w16": {"kernel_avg_us": round(shard_us, 2),
+                            "GBps": round(32 * MiB / (shard_us * 1e-6) / 1e9, 1),
+                            "frac": round(32 * MiB / (shard_us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
+                            "note": "one GPU's share of a 256 MiB array split over 8 GPUs; "
+                                    "32 distinct 32 MiB slices in rotation"},
+        "config1_2MiB_w16": {"kernel_median_us": round(small_ms[len(small_ms) // 2] * 1e3, 2),
+                             "kernel_GBps": round(2 * MiB / (small_ms[len(small_ms) // 2] * 1e-3) / 1e9, 1),
+                             "wall_us_per_call": round(small_wall_us, 2),
+                             "note": "latency-bound: one kernel launch per 2 MiB"},
         "frac_of_read_roofline": round(achieved / rl_gbps, 4),
     }
     del bufs

@@ -44,13 +44,13 @@ def want_for(host, t, i):
     return oracle.pospopcnt(host[base:base + n], w)
 
 
-def alone_plain(ppc, dev_pool, t):
+def alone_plain(ppc, dev_pool, t, col_bytes=COL_BYTES):
     n = len(t["length"])
     counts = torch.zeros((n, 64), dtype=torch.int64, device="cuda:0")
     lib = ppc.lib()
     st = torch.cuda.current_stream().cuda_stream
     for i in range(n):
-        addr = dev_pool.data_ptr() + int(t["column"][i]) * COL_BYTES + int(t["offset"][i])
+        addr = dev_pool.data_ptr() + int(t["column"][i]) * col_bytes + int(t["offset"][i])
         assert lib.ppc_pospopcnt(int(t["width"][i]), counts.data_ptr() + i * 512, addr,
                                  int(t["length"][i]), st) == 0
     torch.cuda.synchronize()
@@ -169,5 +169,47 @@ def test_onehot_u32_columns_count_the_histogram(ppc):
         for k, (c, a, b) in enumerate(reqs):
             hist = np.bincount(cats[c * words + a:c * words + b], minlength=32)
             assert np.array_equal(np.array(results[k].counts[:32], dtype=np.uint64), hist)
+    finally:
+        ppc.ppc_server_destroy(server)
+
+
+def test_full_size_pool_at_half_load(ppc):
+    """The serving workload at full size, in the default server
+    configuration the bench times: a 1 GiB pool of one-hot uint32 columns
+    (16 x 64 MiB, 32 categories, Zipf s = 1.0) and 20,000 Poisson requests
+    (64 B .. 64 MiB, unaligned) offered at about half the plain kernel's
+    bandwidth.  Every result equals the plain call on the same bytes, a
+    seeded sample equals the oracle, and sampled requests served alone
+    equal their result in the mix (tolerance 0)."""
+    col = 64 * MiB
+    n = 20_000
+    pool = synth.device_onehot_u32_columns(16, col // 4, seed=4, device="cuda:0")
+    torch.cuda.synchronize()
+    rate = 0.5 * 6.5e12 / synth.log_uniform_mean(64, 64 * MiB)
+    t = synth.serve_trace(n, seed=4, n_columns=16, column_bytes=col, rate_per_s=rate, lo=64, hi=64 * MiB)
+    server = ppc.ppc_server_create(pool, column_bytes=col)
+    try:
+        results, stats = ppc.ppc_server_run_trace(server, t["column"], t["width"], t["offset"], t["length"],
+                                                  t["arrival_ns"])
+        assert stats["n_requests"] == n and stats["mean_batch"] > 1.0
+        plain = alone_plain(ppc, pool, t, col_bytes=col)
+        for i in range(n):
+            r = results[i]
+            w = int(t["width"][i])
+            assert r.tag == i and r.status == 0 and r.width == w
+            assert np.array_equal(np.array(r.counts[:w], dtype=np.uint64), plain[i, :w]), "request %d" % i
+        rng = np.random.default_rng(7)
+        for i in rng.choice(n, size=60, replace=False):
+            i = int(i)
+            base = int(t["column"][i]) * col + int(t["offset"][i])
+            host = pool[base:base + int(t["length"][i])].cpu().numpy()
+            w = int(t["width"][i])
+            assert np.array_equal(np.array(results[i].counts[:w], dtype=np.uint64), oracle.pospopcnt(host, w))
+        for i in rng.choice(n, size=20, replace=False):
+            i = int(i)
+            w = int(t["width"][i])
+            got = np.array(results[i].counts[:w], dtype=np.uint64)
+            t_one = {k: t[k] for k in ("column", "width", "offset", "length")}
+            assert np.array_equal(served_alone(ppc, server, t_one, i), got)
     finally:
         ppc.ppc_server_destroy(server)
