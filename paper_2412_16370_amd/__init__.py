@@ -153,10 +153,14 @@ def _ptr(x) -> int | None:
 
 
 def _nbytes(buf, nbytes):
+    size = buf.numel() * buf.element_size() if hasattr(buf, "numel") else None
     if nbytes is not None:
-        return int(nbytes)
-    if hasattr(buf, "numel"):
-        return buf.numel() * buf.element_size()
+        nbytes = int(nbytes)
+        if nbytes < 0 or (size is not None and nbytes > size):
+            raise ValueError("nbytes=%d outside the %s-byte tensor" % (nbytes, size))
+        return nbytes
+    if size is not None:
+        return size
     raise ValueError("nbytes is required for a raw address")
 
 

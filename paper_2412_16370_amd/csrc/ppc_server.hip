@@ -10,13 +10,15 @@
 // retires finished batches and, whenever one of its K streams is idle and
 // requests are pending, launches them as one batch right away: pending
 // requests that arrived while other batches were on the GPU are taken in
-// arrival order, so work of several batches overlaps on the device.  Each
-// batch is: tables host->device, clear of its counters, the persistent
-// batched kernel (the same arithmetic as the plain call), counters
-// device->host -- captured once per stream as a hipGraph, so a batch costs
-// the host one graph launch and one event record -- then an event.  A
-// request's result is identical to what the plain call computes for it
-// alone.
+// arrival order, so work of several batches overlaps on the device.  The
+// host writes a batch's tables into its stream's pinned staging buffer and
+// replays that stream's graph, captured once: a kernel copies the tables to
+// the device, the persistent batched kernel counts (the same arithmetic as
+// the plain call), and an epilogue kernel writes the counters into pinned
+// host memory, clears them and re-arms the work cursor.  An event recorded
+// after the replay marks the batch done, so a batch costs the host one
+// graph launch and one event record.  A request's result is identical to
+// what the plain call computes for it alone.
 //
 // Threading: a server object is used from one host thread at a time.
 #include <hip/hip_runtime.h>
@@ -32,6 +34,7 @@
 
 #include "ppc.h"
 #include "ppc_batch.hpp"
+#include "ppc_device.hpp"
 #include "ppc_host.hpp"
 
 namespace ppc {
@@ -162,7 +165,8 @@ void dispatch(ppc_server *s) {
                             reinterpret_cast<uint64_t *>(l.counts_dev + (uint64_t)n * 64), rq.width);
             // a request never needs more than a quarter of the item table
             uint32_t p = s->cfg.tiles_per_item;
-            while (items_needed(ai, p) > s->item_cap / 4) p *= 2;
+            while (items_needed(ai, p) > s->item_cap / 4 && p < kMaxItemTiles) p *= 2;
+            p = std::min(p, kMaxItemTiles);
             const uint32_t need = items_needed(ai, p);
             if (n > 0 && n_items + need > s->item_cap) break;
             arrays[n] = ai;
@@ -204,6 +208,11 @@ ppc_status validate(const ppc_server *s, const ppc_request *r) {
     if (!(r->width == 8 || r->width == 16 || r->width == 32 || r->width == 64)) return PPC_EINVAL;
     if (r->column >= s->n_columns) return PPC_EINVAL;
     if (r->offset > s->column_bytes || r->nbytes > s->column_bytes - r->offset) return PPC_EINVAL;
+    // dispatch() fits one request into a quarter of the item table, with at
+    // most kMaxItemTiles tiles per item: larger requests are refused
+    const uint64_t tile_bytes = (uint64_t)kTileChunks * 16u;
+    const uint64_t max_tiles = (uint64_t)(s->item_cap / 4u) * kMaxItemTiles;
+    if (r->nbytes / tile_bytes + 2u > max_tiles) return PPC_EINVAL;
     return PPC_OK;
 }
 

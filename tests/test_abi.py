@@ -89,3 +89,22 @@ def test_stream_and_popcount_validation(lib):
     assert lib.ppc_popcount(fake + 4, fake, 10, None) == 1
     assert lib.ppc_popcount(fake, None, 10, None) == 1
     assert lib.ppc_popcount(fake, None, 0, None) == 0
+
+
+def test_binding_bounds_nbytes_by_the_tensor():
+    """The binding refuses a byte count larger than the tensor it is given,
+    so a length mistake cannot turn into a read past the buffer."""
+    torch = pytest.importorskip("torch")
+    import paper_2412_16370_amd as ppc
+
+    t = torch.zeros(10, dtype=torch.uint8)
+    assert ppc._nbytes(t, None) == 10
+    assert ppc._nbytes(t, 7) == 7
+    assert ppc._nbytes(torch.zeros(3, dtype=torch.int64), None) == 24
+    with pytest.raises(ValueError):
+        ppc._nbytes(t, 11)
+    with pytest.raises(ValueError):
+        ppc._nbytes(t, -1)
+    with pytest.raises(ValueError):
+        ppc._nbytes(0x1000, None)   # a raw address needs its length
+    assert ppc._nbytes(0x1000, 5) == 5
