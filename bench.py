@@ -337,11 +337,19 @@ def main():
         c16 = torch.zeros(16, dtype=torch.int64, device=dev)
         res = {}
         for v in (0, 1, 2):
-            ms = time_calls(lambda b, i: ppc.ppc_pospopcnt_variant(v, 16, c16, b), abufs, 12, torch)
-            med = sorted(ms)[len(ms) // 2]
-            res["variant%d" % v] = {"us": round(med * 1e3, 2),
-                                    "GBps": round(CALL_BYTES / (med * 1e-3) / 1e9, 1)}
-            log("variant %d: %.2f us, %.1f GB/s" % (v, med * 1e3, CALL_BYTES / (med * 1e-3) / 1e9))
+            # back-to-back calls over the rotating buffers, host clock between
+            # two synchronisations (the same for every variant)
+            for i in range(4):
+                ppc.ppc_pospopcnt_variant(v, 16, c16, abufs[i % 4])
+            torch.cuda.synchronize()
+            reps = 40
+            t0 = time.perf_counter()
+            for i in range(reps):
+                ppc.ppc_pospopcnt_variant(v, 16, c16, abufs[i % 4])
+            torch.cuda.synchronize()
+            us = (time.perf_counter() - t0) / reps * 1e6
+            res["variant%d" % v] = {"us_per_call": round(us, 2), "GBps": round(CALL_BYTES / (us * 1e-6) / 1e9, 1)}
+            log("variant %d: %.2f us per call, %.1f GB/s" % (v, us, CALL_BYTES / (us * 1e-6) / 1e9))
         print(json.dumps({"ablation_256MiB_w16": res}), flush=True)
         return
 
