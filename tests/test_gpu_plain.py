@@ -11,6 +11,8 @@ the oracle bit for bit.  Cases:
   * a 64 MiB one-hot column (counts equal the category histogram);
   * small grids that force many overflow segments per wave;
   * a buffer just over 4 GiB with a ragged tail;
+  * an input over one launch's tile budget (16 GiB at a one-wave grid),
+    split into two launches;
   * accumulation into non-zero counters, repeatability, side streams.
 """
 import ctypes
@@ -158,6 +160,23 @@ def test_just_over_4GiB_ragged(geometry):
     host = buf.cpu().numpy()
     want = oracle.pospopcnt_mt(host[5:], 64, HOST_THREADS)
     del buf
+    assert np.array_equal(got, want)
+
+
+def test_input_split_into_several_launches(geometry):
+    """A launch gives no wave more than 2^20 tiles of 16 KiB (its 32-bit
+    counts stay below 2^31).  With the grid capped at one wave the budget is
+    16 GiB per launch, so 16 GiB + 12,345 bytes from an unaligned start takes
+    two launches with the same pointer residue."""
+    ppc = geometry
+    ppc.ppc_set_plain_geometry(1, 2)
+    n = (16 << 30) + 12345 + 5
+    buf = synth.device_bernoulli(n, 0.5, seed=17, device=dev())
+    got = run(ppc, 32, buf[5:])
+    host = buf.cpu().numpy()
+    del buf
+    torch.cuda.empty_cache()
+    want = oracle.pospopcnt_mt(host[5:], 32, HOST_THREADS)
     assert np.array_equal(got, want)
 
 
