@@ -255,7 +255,8 @@ def size_sweep(ppc, torch, synth, dev, out_path):
     buf = synth.device_bernoulli(sizes[-1], 0.5, seed=60, device=dev)
     sink = torch.zeros(1, dtype=torch.int64, device=dev)
     lib, st = ppc.lib(), torch.cuda.current_stream().cuda_stream
-    os.makedirs(os.path.dirname(out_path), exist_ok=True)
+    if os.path.dirname(out_path):
+        os.makedirs(os.path.dirname(out_path), exist_ok=True)
     with open(out_path, "w") as out:
         for n in sizes:
             row = {"bytes": n}
@@ -319,7 +320,8 @@ def main():
                     help="length sweep of Section 5.2 (2^i and 3*2^i bytes up to 1.5 GiB) at every "
                          "width, repeated calls on one buffer as in the paper's harness; writes "
                          "JSON lines to --sweep-out and exits")
-    ap.add_argument("--sweep-out", default=os.path.join(ROOT, "gpurun_out", "size_sweep.jsonl"))
+    ap.add_argument("--sweep-out", default="size_sweep.jsonl",
+                    help="JSON-lines file for --sweep (one line per size)")
     ap.add_argument("--ablation", action="store_true",
                     help="time the three accumulation schedules (ppc_pospopcnt_variant 0/1/2) on "
                          "256 MiB at w = 16 and exit (short: also the command to profile them)")
