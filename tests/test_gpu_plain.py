@@ -210,6 +210,42 @@ def test_repeatable_and_on_a_side_stream(geometry):
         assert np.array_equal(o, want)
 
 
+def test_host_threads_on_their_own_streams(geometry):
+    """Plain calls from four host threads at once (ctypes drops the GIL for
+    the call), each thread on its own stream; every thread adds into its own
+    counters and into one shared set (atomics commute), 25 calls each."""
+    import threading
+
+    ppc = geometry
+    host = [synth.random_bytes((3 << 20) + 11 * k, seed=90 + k) for k in range(4)]
+    bufs = [torch.from_numpy(h).to(dev()) for h in host]
+    own = [torch.zeros(16, dtype=torch.int64, device=dev()) for _ in range(4)]
+    shared = torch.zeros(16, dtype=torch.int64, device=dev())
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(k):
+        try:
+            for _ in range(25):
+                ppc.ppc_pospopcnt16(own[k], bufs[k][k:], stream=streams[k])
+                ppc.ppc_pospopcnt16(shared, bufs[k][k:], stream=streams[k])
+        except Exception as e:  # reported below, in the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=work, args=(k,)) for k in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors
+    want = [oracle.pospopcnt(h[k:], 16) for k, h in enumerate(host)]
+    for k in range(4):
+        assert np.array_equal(ppc.counts_to_numpy(own[k]), want[k] * np.uint64(25))
+    assert np.array_equal(ppc.counts_to_numpy(shared), sum(want) * np.uint64(25))
+
+
 def test_errors_reported_not_raised_on_device(geometry):
     ppc = geometry
     buf = torch.zeros(64, dtype=torch.uint8, device=dev())
