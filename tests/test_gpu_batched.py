@@ -206,3 +206,34 @@ def test_empty_plan_and_bad_descriptors(ppc):
         assert e.value.status == ppc.PPC_EINVAL
     torch.cuda.synchronize()
     assert not counts.any()
+
+
+@pytest.mark.parametrize("w", (8, 16, 32, 64))
+def test_every_short_length_and_offset_in_one_plan(ppc, w):
+    """The short sweep of the plain-call tests -- every length 0..4096 at
+    every start offset 0..63, between 0xFF guard bytes -- as ONE batched
+    plan of 262,208 arrays, run twice (the replay adds the same counts
+    again).  Covers the batched walk of empty arrays, head/tail-only arrays,
+    short single-chunk arrays and partial tiles on every case."""
+    max_len, n_off, lo, hi = 4096, 64, 64, 128
+    region = synth.random_bytes(max_len + n_off, seed=2)
+    host = np.concatenate([np.full(lo, 0xFF, np.uint8), region, np.full(hi, 0xFF, np.uint8)])
+    buf = torch.from_numpy(host).to(dev())
+    rows = n_off * (max_len + 1)
+    counts = torch.zeros((rows, w), dtype=torch.int64, device=dev())
+    base, cbase = buf.data_ptr() + lo, counts.data_ptr()
+    addrs = [base + o for o in range(n_off) for _ in range(max_len + 1)]
+    lens = [n for _ in range(n_off) for n in range(max_len + 1)]
+    descs = ppc.make_descs(addrs, lens, [cbase + r * w * 8 for r in range(rows)], [w] * rows)
+    plan = ppc.ppc_plan_create(descs, rows, ppc.ppc_plan_opts(16, 0, 0, 1, 0))
+    try:
+        want = oracle.sweep(region, w, max_len, n_off)
+        for rep in (1, 2):
+            ppc.ppc_plan_run(plan)
+            torch.cuda.synchronize()
+            got = ppc.counts_to_numpy(counts).reshape(n_off, max_len + 1, w)
+            bad = np.argwhere((got != want * np.uint64(rep)).any(axis=2))
+            assert bad.size == 0, "run %d, first mismatches (offset, length): %s" % (rep, bad[:5].tolist())
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    assert np.array_equal(buf.cpu().numpy(), host)  # input untouched
