@@ -208,10 +208,10 @@ ppc_status ppc_plan_destroy(ppc_plan *plan);
  * ---------------------------------------------------------------------- */
 typedef struct ppc_server_cfg {
     uint32_t n_streams;      /* batches in flight at once (0 = 3)             */
-    uint32_t max_batch;      /* requests per batch (0 = 1024)                 */
+    uint32_t max_batch;      /* requests per batch (0 = 4096)                 */
     uint32_t max_inflight;   /* result slots = admitted requests (0 = 16384)  */
     uint32_t tiles_per_item; /* 16 KiB tiles per work item (0 = 16)           */
-    uint64_t inflight_bytes; /* admission budget in bytes (0 = 4 GiB)         */
+    uint64_t inflight_bytes; /* admission budget in bytes (0 = 16 GiB)        */
     uint32_t waves;          /* persistent grid per batch (0 = 8 per CU)      */
     uint32_t reserved;       /* must be 0                                     */
 } ppc_server_cfg;
