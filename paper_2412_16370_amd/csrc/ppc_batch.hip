@@ -383,7 +383,7 @@ ppc_status autotune(ppc_plan *p, hipStream_t st, uint32_t &best_p, uint32_t &bes
     if (rc == PPC_OK &&
         hipMemcpyAsync(tune_dev, tune.data(), n * sizeof(ArrayInfo), hipMemcpyHostToDevice, st) != hipSuccess)
         rc = PPC_EDEVICE;
-    const uint32_t cand_p[] = {4, 16, 64, 256};
+    const uint32_t cand_p[] = {4, 16, 64, 256, 1024};
     const uint32_t cand_w[] = {4, 8, 16};
     float best = 1e30f;
     for (uint32_t cp : cand_p)
