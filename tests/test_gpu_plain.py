@@ -148,7 +148,7 @@ def test_small_grids_force_many_segments(geometry, waves, wpb):
     ppc.ppc_set_plain_geometry(waves, wpb)
     host = synth.random_bytes((32 << 20) + 77, seed=waves)
     buf = torch.from_numpy(host).to(dev())
-    for w, off in ((8, 0), (64, 9)):  # below and above the streaming-load size
+    for w, off in ((8, 0), (64, 9)):  # aligned and unaligned starts
         got = run(ppc, w, buf[off:])
         assert np.array_equal(got, oracle.pospopcnt_mt(host[off:], w, HOST_THREADS))
 
