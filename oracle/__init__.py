@@ -170,9 +170,3 @@ def column_counts(vectors: list[int], nbits: int) -> list[int]:
     the quantity a carry-save adder network compresses (Section 3.2)."""
     return [sum((v >> i) & 1 for v in vectors) for i in range(nbits)]
 
-
-def batched(arrays) -> list[np.ndarray]:
-    """Batched form: each (data, w) pair is an independent call of
-    :func:`pospopcnt` (the same operation per array, width applied per array,
-    Section 5: one kernel, the accumulation function picks the width)."""
-    return [pospopcnt(d, w) for d, w in arrays]

@@ -122,3 +122,19 @@ def test_empty_and_bad_arguments():
 def test_popcount_matches_unpackbits():
     data = synth.random_bytes(5000, seed=21)
     assert oracle.popcount(data) == int(np.unpackbits(data).sum())
+
+
+@pytest.mark.parametrize("w", WIDTHS)
+def test_window_sweep_matches_the_streams_statement(w):
+    """oracle.sweep (every window data[o:o+n]) is what the GPU sweep tests
+    compare against: each of its windows must equal the independent
+    interleaved-streams statement of Section 1 on the same bytes, laid out
+    as (offset, length, counter)."""
+    data = synth.random_bytes(40 + 9, seed=w)
+    got = oracle.sweep(data, w, 40, 9)
+    assert got.shape == (9, 41, w) and got.dtype == np.uint64
+    for o in range(9):
+        for n in range(41):
+            assert got[o, n].tolist() == oracle.pospopcnt_streams(bytes(data[o:o + n]), w), (o, n)
+    with pytest.raises(ValueError):
+        oracle.sweep(data[:40], w, 40, 9)  # the last window would run past the buffer
