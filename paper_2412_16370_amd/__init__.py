@@ -133,6 +133,13 @@ def lib():
             raise RuntimeError(
                 "libppc.so is not built (expected at %s); run "
                 "`python -c 'import __graft_entry__ as g; g.build()'`" % LIB_PATH)
+        # torch ships its own HIP runtime under the same soname.  Loaded
+        # first, it is the runtime libppc.so binds to; loaded after
+        # libppc.so, it would come in as a second runtime whose streams and
+        # allocations the library's runtime does not know (launches on
+        # torch's streams then fail).
+        import torch  # noqa: F401
+
         _lib = _declare(ctypes.CDLL(LIB_PATH))
     return _lib
 

@@ -108,3 +108,24 @@ def test_binding_bounds_nbytes_by_the_tensor():
     with pytest.raises(ValueError):
         ppc._nbytes(0x1000, None)   # a raw address needs its length
     assert ppc._nbytes(0x1000, 5) == 5
+
+
+def test_library_and_torch_share_one_hip_runtime():
+    """torch bundles its own HIP runtime under the soname libppc.so links
+    against.  Loading the library before torch (here: a call that needs no
+    tensor) must still leave one runtime in the process, or torch's streams
+    are unknown to the library's launches."""
+    import ast
+    import subprocess
+    import sys
+
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_2412_16370_amd as ppc\n"
+        "ppc.lib().ppc_version()\n"
+        "import torch\n"
+        "print(sorted({ln.split()[-1] for ln in open('/proc/self/maps') if 'libamdhip64' in ln}))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    runtimes = ast.literal_eval(out.stdout.strip().splitlines()[-1])
+    assert len(runtimes) == 1, runtimes
