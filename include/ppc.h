@@ -111,7 +111,8 @@ ppc_status ppc_pospopcnt_variant(unsigned variant, unsigned width, uint64_t *cou
 
 /* ------------------------------------------------------------------------
  * Launch geometry of the plain call.  `waves` caps the number of wavefronts
- * the grid holds (0 = the library default: 8 per compute unit);
+ * the grid holds (0 = the library default: one 8-wave block on each of 3/4
+ * of the compute units, which streams faster than a block on every one);
  * `waves_per_block` is 2, 4 or 8 (default 8).  Applies to later plain calls
  * from any thread on any device.  Returns PPC_EINVAL for values out of range.
  * ---------------------------------------------------------------------- */

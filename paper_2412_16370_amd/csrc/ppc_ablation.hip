@@ -212,7 +212,7 @@ extern "C" ppc_status ppc_pospopcnt_variant(unsigned variant, unsigned width, ui
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
     constexpr int kWpb = 8;
-    const uint64_t waves = std::min<uint64_t>(std::max<uint32_t>(ai.n_tiles, 1u), plain_wave_cap(dev));
+    const uint64_t waves = std::min<uint64_t>(std::max<uint32_t>(ai.n_tiles, 1u), full_grid_wave_cap(dev));
     const unsigned blocks = (unsigned)((waves + kWpb - 1) / kWpb);
     // a wave adds at most 2^11 per position per tile: keep its 32-bit
     // counts below 2^31 (one launch, no splitting, for this measurement path)

@@ -20,7 +20,12 @@ ppc_status plain_pospopcnt(unsigned width, uint64_t *counts, const void *buf, si
 ppc_status plain_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, uint64_t offset,
                               hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 
-// Wave cap of the plain call's grid on a device.
+// Wave cap of the plain call's grid on a device: the value set with
+// ppc_set_plain_geometry, else one 8-wave block on 3/4 of the CUs.
 unsigned plain_wave_cap(int device);
+
+// The same override, else one 8-wave block on every CU (the grid of the
+// accumulation-schedule variants, whose extra ALU work wants every CU).
+unsigned full_grid_wave_cap(int device);
 
 }  // namespace ppc
