@@ -297,10 +297,20 @@ __device__ __forceinline__ uint4 load_stream(const uint4 *p) {
     return make_uint4(r.x, r.y, r.z, r.w);
 }
 
+// The 16 loads of a tile are issued in chunk order (the scheduling barrier
+// keeps the compiler from reordering them).  Loads complete in issue order,
+// so the carry-save network, which takes the chunks in that order, can start
+// on the first pairs while the rest are in flight: the compiler's wait counts
+// step down two loads at a time instead of waiting for nearly the whole tile.
+// That matters for the last tile of each wave, whose compression is on the
+// kernel's critical path (256 MiB: -0.5 us; it also frees 25 VGPRs).
 template <bool NT>
 __device__ __forceinline__ void load_tile(uint4 (&v)[kLoadsPerTile], const uint4 *p) {
 #pragma unroll
-    for (int j = 0; j < kLoadsPerTile; ++j) v[j] = NT ? load_stream(p + j * kWave) : p[j * kWave];
+    for (int j = 0; j < kLoadsPerTile; ++j) {
+        v[j] = NT ? load_stream(p + j * kWave) : p[j * kWave];
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 // One wave's share of a body of 16-byte chunks: tiles t0, t0+stride, ... that

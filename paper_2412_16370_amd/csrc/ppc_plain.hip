@@ -86,8 +86,10 @@ typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ void load_tile_u64(u64x2 (&v)[kLoadsPerTile], const uint4 *p) {
 #pragma unroll
-    for (int j = 0; j < kLoadsPerTile; ++j)
+    for (int j = 0; j < kLoadsPerTile; ++j) {
         v[j] = __builtin_nontemporal_load(reinterpret_cast<const u64x2 *>(p + j * kWave));
+        __builtin_amdgcn_sched_barrier(0);  // issue order = chunk order, as in load_tile
+    }
 }
 
 template <int WPB>
