@@ -237,3 +237,41 @@ def test_every_short_length_and_offset_in_one_plan(ppc, w):
     finally:
         ppc.ppc_plan_destroy(plan)
     assert np.array_equal(buf.cpu().numpy(), host)  # input untouched
+
+
+@pytest.mark.parametrize("tiles_per_item", (0, 1 << 18))
+def test_arrays_beyond_4GiB_in_one_plan(ppc, tiles_per_item, tmp_path, monkeypatch):
+    """Maximum sizes in the batched form: a 5 GiB + 13-byte array (over 2^18
+    tiles of 16 KiB) from an unaligned start and a 1 GiB array, next to small
+    ragged arrays, in one plan.  With 2^18 tiles per item the big array
+    becomes one item of 4 GiB and one of the rest; with the tuned setting it
+    becomes thousands.  Every array must match the oracle exactly."""
+    monkeypatch.setenv("PPC_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    big, mid = (5 << 30) + 13, 1 << 30
+    small = [1, 15, 17, 4095, 16 * 1024 + 3, MiB + 77]
+    lengths = [big, mid] + small
+    widths = [32, 64, 8, 16, 32, 64, 8, 16]
+    starts, pos = [], 3  # the first array starts 3 bytes past a 16-byte boundary
+    for n in lengths:
+        starts.append(pos)
+        pos += n + 29
+    buf = synth.device_bernoulli(pos + 64, 0.5, seed=23, device=dev())
+    counts = torch.zeros((len(lengths), 64), dtype=torch.int64, device=dev())
+    base, cbase = buf.data_ptr(), counts.data_ptr()
+    descs = ppc.make_descs([base + s for s in starts], lengths, [cbase + i * 512 for i in range(len(lengths))],
+                           widths)
+    opts = ppc.ppc_plan_opts(tiles_per_item, 0, 1 if tiles_per_item == 0 else 0, 1, 0)
+    plan = ppc.ppc_plan_create(descs, len(lengths), opts)
+    try:
+        ppc.ppc_plan_run(plan)
+        torch.cuda.synchronize()
+        got = ppc.counts_to_numpy(counts)
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    host = buf.cpu().numpy()
+    del buf
+    torch.cuda.empty_cache()
+    for i, (s, n, w) in enumerate(zip(starts, lengths, widths)):
+        want = oracle.pospopcnt_mt(host[s:s + n], w, 16)
+        assert np.array_equal(got[i, :w], want), (i, n, w)
+        assert not got[i, w:].any()
