@@ -324,7 +324,7 @@ def size_sweep(ppc, torch, synth, dev, out_path):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--kernel-seconds", type=float, default=1.0,
                     help="accumulated kernel time of the event-timed pass (at least --steps steps)")
     ap.add_argument("--warmup", type=int, default=3)
