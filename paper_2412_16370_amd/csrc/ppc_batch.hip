@@ -62,20 +62,24 @@ __device__ __forceinline__ void run_item(const ArrayInfo *__restrict__ arrays, c
 }
 
 // The persistent loop of one wave (index gw of nw): group gw first, then
-// groups nw + ticket while the cursor hands out tickets below the end.  The
-// next ticket is requested before the current group runs, so its latency
-// hides behind the group's work; a wave's first group needs no ticket, so
-// the launch does not start with every wave queueing on one atomic.
+// groups nw + ticket while the cursor hands out tickets below the end.  A
+// wave's first group needs no ticket, so the launch does not start with
+// every wave queueing on one atomic.  The next ticket is taken only once
+// the current group is done: a ticket taken in advance reserves a group
+// for the whole of the current one, and near the end short groups then
+// wait behind long ones while other waves are idle (10,000-array mix, 4 MiB
+// items: a ~190 us tail, 6.6 against 6.9 TB/s).  The ticket's latency is
+// small against a group (at least 16 tiles).
 __device__ __forceinline__ void run_groups(const ArrayInfo *__restrict__ arrays, const WorkItem *__restrict__ items,
                                            const uint32_t *__restrict__ groups, uint32_t n_groups, uint32_t *cursor,
                                            uint32_t gw, uint32_t nw) {
     const uint32_t lane = __lane_id();
     uint32_t grp = gw;
     while (grp < n_groups) {
-        uint32_t ticket = 0;
-        if (lane == 0) ticket = atomicAdd(cursor, 1u);
         const uint32_t i0 = groups[grp], i1 = groups[grp + 1];
         for (uint32_t i = i0; i < i1; ++i) run_item(arrays, items[i]);
+        uint32_t ticket = 0;
+        if (lane == 0) ticket = atomicAdd(cursor, 1u);
         grp = nw + (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
     }
 }
