@@ -213,3 +213,30 @@ def test_full_size_pool_at_half_load(ppc):
             assert np.array_equal(served_alone(ppc, server, t_one, i), got)
     finally:
         ppc.ppc_server_destroy(server)
+
+
+def test_edge_requests_in_one_batch(ppc, pool):
+    """Empty requests, single bytes at both ends of a column, whole columns,
+    requests ending on a column's last byte and ragged ones, every width,
+    all arriving at once (one or two batches): each equals the oracle."""
+    host, dev_pool = pool
+    reqs = []
+    for w in (8, 16, 32, 64):
+        for c in (0, N_COL - 1):
+            reqs += [(c, w, 0, 0), (c, w, COL_BYTES, 0), (c, w, 0, 1), (c, w, COL_BYTES - 1, 1),
+                     (c, w, 0, COL_BYTES), (c, w, 7, COL_BYTES - 7), (c, w, 5, 16 * 1024 + 3),
+                     (c, w, COL_BYTES - 1000, 1000), (c, w, 13, 31)]
+    t = dict(column=[r[0] for r in reqs], width=[r[1] for r in reqs], offset=[r[2] for r in reqs],
+             length=[r[3] for r in reqs], arrival_ns=[0] * len(reqs))
+    server = ppc.ppc_server_create(dev_pool, column_bytes=COL_BYTES)
+    try:
+        results, stats = ppc.ppc_server_run_trace(server, t["column"], t["width"], t["offset"], t["length"],
+                                                  t["arrival_ns"])
+        for i, (c, w, o, n) in enumerate(reqs):
+            r = results[i]
+            assert r.tag == i and r.status == 0 and r.width == w
+            want = oracle.pospopcnt(host[c * COL_BYTES + o:c * COL_BYTES + o + n], w)
+            assert np.array_equal(np.array(r.counts[:w], dtype=np.uint64), want), (c, w, o, n)
+            assert not any(r.counts[w:])
+    finally:
+        ppc.ppc_server_destroy(server)
