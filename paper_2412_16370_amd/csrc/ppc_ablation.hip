@@ -133,7 +133,7 @@ __device__ __forceinline__ uint32_t wave_count_variant(const uint4 *body, uint64
             }
         } else {
             uint4 v[kLoadsPerTile];
-            load_tile<true>(v, p);
+            load_tile(v, p);
             add_tile(v);
         }
     }

@@ -57,7 +57,7 @@ __device__ __forceinline__ void run_item(const ArrayInfo *__restrict__ arrays, c
         }
     }
     const uint32_t acc =
-        wave_count_tiles<true>(ai.body, ai.n_chunks, ai.n_full, it.tile0, it.tile1, 1u, edge, has_edge);
+        wave_count_tiles(ai.body, ai.n_chunks, ai.n_full, it.tile0, it.tile1, 1u, edge, has_edge);
     fold_add(acc, ai.width, ai.m, ai.counts);
 }
 

@@ -304,11 +304,10 @@ __device__ __forceinline__ uint4 load_stream(const uint4 *p) {
 // step down two loads at a time instead of waiting for nearly the whole tile.
 // That matters for the last tile of each wave, whose compression is on the
 // kernel's critical path (256 MiB: -0.5 us; it also frees 25 VGPRs).
-template <bool NT>
 __device__ __forceinline__ void load_tile(uint4 (&v)[kLoadsPerTile], const uint4 *p) {
 #pragma unroll
     for (int j = 0; j < kLoadsPerTile; ++j) {
-        v[j] = NT ? load_stream(p + j * kWave) : p[j * kWave];
+        v[j] = load_stream(p + j * kWave);
         __builtin_amdgcn_sched_barrier(0);
     }
 }
@@ -324,7 +323,6 @@ __device__ __forceinline__ void load_tile(uint4 (&v)[kLoadsPerTile], const uint4
 // the current tile, so the compiler's wait counts let those loads stay in
 // flight (a conditional load there makes it wait for them).  The last one
 // or two whole tiles are peeled off after the loop.
-template <bool NT>
 __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t n_chunks, uint32_t n_full,
                                                      uint32_t t0, uint32_t t_end, uint32_t stride, uint4 edge,
                                                      bool has_edge) {
@@ -368,13 +366,13 @@ __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t
     if (n_mine > 0) {
         any = true;
         uint4 va[kLoadsPerTile], vb[kLoadsPerTile];
-        load_tile<NT>(va, tile_ptr(0));
+        load_tile(va, tile_ptr(0));
         uint32_t i = 0;
         while (i + 2u < n_mine) {  // tiles i (in va), i+1, i+2 exist
-            load_tile<NT>(vb, tile_ptr(i + 1u));
+            load_tile(vb, tile_ptr(i + 1u));
             __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the math
             add_tile(va);
-            load_tile<NT>(va, tile_ptr(i + 2u));
+            load_tile(va, tile_ptr(i + 2u));
             __builtin_amdgcn_sched_barrier(0);
             add_tile(vb);
             i += 2u;
@@ -385,7 +383,7 @@ __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t
             }
         }
         if (i + 1u < n_mine) {  // two tiles left: i in va, i+1
-            load_tile<NT>(vb, tile_ptr(i + 1u));
+            load_tile(vb, tile_ptr(i + 1u));
             __builtin_amdgcn_sched_barrier(0);
             add_tile(va);
             add_tile(vb);

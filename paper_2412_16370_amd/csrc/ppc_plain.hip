@@ -43,14 +43,14 @@ struct PlainArgs {
     uint32_t m;                 // slot of buf's first byte subtracted from address slots (mod w/8)
 };
 
-// WPB: waves per block; NT: streaming (non-temporal) loads, which every
-// launch uses: each byte is read once, and against inputs in DRAM the
-// streaming hint is never slower (up to 20 % faster on inputs of a few MiB,
-// ~10 % on long streams) than the cached policies.  Each wave
-// walks tiles gw, gw + nw, ... (nw = waves in the grid), so one load
-// instruction of a wave reads 1 KiB and the 16 loads of a tile 16 KiB, all
-// contiguous; at any moment the grid works on one contiguous window.
-template <int WPB, bool NT>
+// WPB: waves per block.  Loads are streaming (non-temporal): each byte is
+// read once, and against inputs in DRAM the streaming hint is never slower
+// (up to 20 % faster on inputs of a few MiB, ~10 % on long streams) than the
+// cached policies.  Each wave walks tiles gw, gw + nw, ... (nw = waves in
+// the grid), so one load instruction of a wave reads 1 KiB and the 16 loads
+// of a tile 16 KiB, all contiguous; at any moment the grid works on one
+// contiguous window.
+template <int WPB>
 __global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wib = wave_in_block();
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
         }
     }
     const uint32_t acc =
-        wave_count_tiles<NT>(a.body, a.n_chunks, a.n_full_tiles, gw, a.n_tiles, nw, edge, gw == 0);
+        wave_count_tiles(a.body, a.n_chunks, a.n_full_tiles, gw, a.n_tiles, nw, edge, gw == 0);
 
     __shared__ uint32_t part[WPB][kWave];
     part[wib][lane] = acc;
@@ -150,11 +150,11 @@ struct LaunchEvents {
 
 static hipError_t launch_plain(const PlainArgs &a, unsigned blocks, unsigned wpb, hipStream_t st, LaunchEvents ev) {
     if (wpb == 2)
-        hipExtLaunchKernelGGL((pospop_plain_kernel<2, true>), dim3(blocks), dim3(128), 0, st, ev.start, ev.stop, 0, a);
+        hipExtLaunchKernelGGL((pospop_plain_kernel<2>), dim3(blocks), dim3(128), 0, st, ev.start, ev.stop, 0, a);
     else if (wpb == 4)
-        hipExtLaunchKernelGGL((pospop_plain_kernel<4, true>), dim3(blocks), dim3(256), 0, st, ev.start, ev.stop, 0, a);
+        hipExtLaunchKernelGGL((pospop_plain_kernel<4>), dim3(blocks), dim3(256), 0, st, ev.start, ev.stop, 0, a);
     else
-        hipExtLaunchKernelGGL((pospop_plain_kernel<8, true>), dim3(blocks), dim3(512), 0, st, ev.start, ev.stop, 0, a);
+        hipExtLaunchKernelGGL((pospop_plain_kernel<8>), dim3(blocks), dim3(512), 0, st, ev.start, ev.stop, 0, a);
     return hipGetLastError();
 }
 
