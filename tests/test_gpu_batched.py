@@ -275,3 +275,31 @@ def test_arrays_beyond_4GiB_in_one_plan(ppc, tiles_per_item, tmp_path, monkeypat
         want = oracle.pospopcnt_mt(host[s:s + n], w, 16)
         assert np.array_equal(got[i, :w], want), (i, n, w)
         assert not got[i, w:].any()
+
+
+@pytest.mark.parametrize("w", (8, 16, 32, 64))
+def test_pieces_of_one_array_share_counters(ppc, w):
+    """Streamed pieces inside one plan: an array cut at random multiples of
+    8 bytes from its (unaligned) start into 300 pieces of uneven length,
+    every piece a descriptor adding into the same counters.  Positions are
+    relative to each piece's pointer, so at cuts that are multiples of w/8
+    the pieces' counts add up to the whole array's (Section 4, step 1 and
+    its footnote); the atomics make the sum exact in any order."""
+    n = 37 * MiB + 5
+    host = synth.random_bytes(n + 3, seed=60 + w)
+    buf = torch.from_numpy(host).to(dev())
+    rng = np.random.default_rng(w)
+    cuts = np.unique(rng.integers(0, n // 8, size=299) * 8)
+    bounds = [0] + [int(c) for c in cuts if 0 < c < n] + [n]
+    counts = torch.zeros(w, dtype=torch.int64, device=dev())
+    base = buf.data_ptr() + 3
+    k = len(bounds) - 1
+    descs = ppc.make_descs([base + bounds[i] for i in range(k)], [bounds[i + 1] - bounds[i] for i in range(k)],
+                           [counts.data_ptr()] * k, [w] * k)
+    plan = ppc.ppc_plan_create(descs, k, ppc.ppc_plan_opts(16, 0, 0, 1, 0))
+    try:
+        ppc.ppc_plan_run(plan)
+        torch.cuda.synchronize()
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    assert np.array_equal(ppc.counts_to_numpy(counts), oracle.pospopcnt(host[3:], w))
