@@ -111,6 +111,31 @@ def pospopcnt_mt(data, w: int, nthreads: int) -> np.ndarray:
     return out
 
 
+def host_threads() -> int:
+    """Host cores this process may run on (its CPU affinity set)."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
+
+
+def pospopcnt_ranges(data, starts, lengths, widths, threads: int | None = None) -> list:
+    """:func:`pospopcnt` of many ranges data[start:start+length] at their
+    own widths, each range counted by the Fig. 2 word loop on its own (the
+    same call as :func:`pospopcnt`), spread over host threads.  Returns the
+    list of uint64 counter arrays in input order."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    buf = _as_u8(data)
+    jobs = [(int(s), int(n), int(w)) for s, n, w in zip(starts, lengths, widths)]
+    for s, n, w in jobs:
+        if w not in WIDTHS or s < 0 or n < 0 or s + n > buf.size:
+            raise ValueError("range or width out of bounds: %r" % ((s, n, w),))
+    # the C loop runs without the interpreter lock, so threads run in parallel
+    with ThreadPoolExecutor(max_workers=threads or host_threads()) as ex:
+        return list(ex.map(lambda j: pospopcnt(buf[j[0]:j[0] + j[1]], j[2]), jobs))
+
+
 def sweep(data, w: int, max_len: int, n_offsets: int) -> np.ndarray:
     """pospopcnt of every window data[o:o+n], o < n_offsets, n <= max_len.
     Returns an array of shape (n_offsets, max_len + 1, w)."""
@@ -163,10 +188,4 @@ def full_adder(a: int, b: int, c: int) -> tuple[int, int]:
         carry |= (n >> 1) << i
         i += 1
     return carry, total
-
-
-def column_counts(vectors: list[int], nbits: int) -> list[int]:
-    """Number of set bits in each bit column of a list of nbits-wide vectors:
-    the quantity a carry-save adder network compresses (Section 3.2)."""
-    return [sum((v >> i) & 1 for v in vectors) for i in range(nbits)]
 

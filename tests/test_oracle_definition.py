@@ -138,3 +138,25 @@ def test_window_sweep_matches_the_streams_statement(w):
             assert got[o, n].tolist() == oracle.pospopcnt_streams(bytes(data[o:o + n]), w), (o, n)
     with pytest.raises(ValueError):
         oracle.sweep(data[:40], w, 40, 9)  # the last window would run past the buffer
+
+
+def test_ranges_equal_the_streams_statement_per_range():
+    """The threaded per-range helper (used to check full-size GPU batches)
+    gives, range by range and in input order, what the interleaved-streams
+    statement gives for that range alone."""
+    data = synth.random_bytes(4096, seed=17)
+    rng = np.random.default_rng(18)
+    starts = rng.integers(0, 4000, size=300)
+    lengths = [int(rng.integers(0, 4096 - s + 1)) % 97 for s in starts]
+    widths = rng.choice(np.array(WIDTHS), size=300)
+    got = oracle.pospopcnt_ranges(data, starts, lengths, widths, threads=4)
+    assert len(got) == 300
+    for g, s, n, w in zip(got, starts, lengths, widths):
+        assert g.tolist() == oracle.pospopcnt_streams(data[int(s):int(s) + int(n)], int(w))
+
+
+def test_ranges_reject_out_of_bounds_and_bad_widths():
+    data = bytes(64)
+    for bad in (([60], [5], [8]), ([-1], [2], [8]), ([0], [8], [12])):
+        with pytest.raises(ValueError):
+            oracle.pospopcnt_ranges(data, *bad)

@@ -129,14 +129,39 @@ def test_mux_carry_form_equals_full_adder_carry():
         assert total == a ^ b ^ c
 
 
-def test_csa_place_values():
-    # Section 3.2: 15 bits of weight 1 compress to weights (1,2,4,8) and the
-    # column counts are what the compressed accumulators must represent.
+def test_carry_save_network_of_full_adders_keeps_place_values():
+    # Sections 3.2-3.3: a 4-bit carry-save accumulator (planes of weight
+    # 1, 2, 4, 8) takes 16 vectors through 15 full adders arranged as
+    # pairs -> twos -> fours -> eights and emits a plane of weight 16.  For
+    # every bit column, the weighted planes after the step must equal the
+    # weighted planes before it plus the number of input vectors with that
+    # bit set.  The column counts come from numpy's bit unpacking, not from
+    # the full adder, so a wrong carry weight, a swapped carry/sum or a
+    # dropped input fails here.
     rng = np.random.default_rng(3)
-    vecs = [int(x) for x in rng.integers(0, 1 << 32, size=15)]
-    counts = oracle.column_counts(vecs, 32)
-    assert all(0 <= c <= 15 for c in counts)
-    assert sum(counts) == sum(bin(v).count("1") for v in vecs)
+    nbits = 32
+    for _ in range(50):
+        vecs = [int(x) for x in rng.integers(0, 1 << nbits, size=16, dtype=np.uint64)]
+        a1, a2, a4, a8 = (int(x) for x in rng.integers(0, 1 << nbits, size=4, dtype=np.uint64))
+        before = [((a1 >> i) & 1) + 2 * ((a2 >> i) & 1) + 4 * ((a4 >> i) & 1) + 8 * ((a8 >> i) & 1)
+                  for i in range(nbits)]
+        fa = oracle.full_adder
+        twos, fours, eights = [], [], []
+        for k in range(0, 16, 2):
+            c, a1 = fa(a1, vecs[k], vecs[k + 1])
+            twos.append(c)
+        for k in range(0, 8, 2):
+            c, a2 = fa(a2, twos[k], twos[k + 1])
+            fours.append(c)
+        for k in range(0, 4, 2):
+            c, a4 = fa(a4, fours[k], fours[k + 1])
+            eights.append(c)
+        a16, a8 = fa(a8, eights[0], eights[1])
+        planes = np.array(vecs, dtype="<u4").view(np.uint8).reshape(16, 4)
+        column = np.unpackbits(planes, axis=1, bitorder="little").sum(axis=0)
+        for i in range(nbits):
+            after = sum(((p >> i) & 1) << e for e, p in enumerate((a1, a2, a4, a8, a16)))
+            assert after == before[i] + int(column[i]), "bit column %d" % i
 
 
 def test_onehot_age_example():
