@@ -43,7 +43,8 @@ typedef enum ppc_status {
     PPC_EINVAL = 1,  /* invalid argument (bad width, NULL, misaligned ...)  */
     PPC_ENOMEM = 2,  /* a host or device allocation failed                 */
     PPC_EDEVICE = 3, /* a HIP runtime call or kernel launch failed         */
-    PPC_EBUSY = 4    /* not admitted now (serving); retry later            */
+    PPC_EBUSY = 4,   /* not admitted now (serving); retry later            */
+    PPC_ETIMEDOUT = 5 /* a host wait passed its deadline (serving)         */
 } ppc_status;
 
 /* Human-readable name of a status code.  Never NULL. */
@@ -214,7 +215,8 @@ typedef struct ppc_server_cfg {
     uint32_t tiles_per_item; /* 16 KiB tiles per work item (0 = 16)           */
     uint64_t inflight_bytes; /* admission budget in bytes (0 = 16 GiB)        */
     uint32_t waves;          /* persistent grid per batch (0 = 8 per CU)      */
-    uint32_t reserved;       /* must be 0                                     */
+    uint32_t batch_timeout_us; /* deadline of a batch on the device, from its
+                                  launch, in microseconds (0 = 10 s)          */
 } ppc_server_cfg;
 
 typedef struct ppc_request {
@@ -259,7 +261,7 @@ typedef struct ppc_server ppc_server;
  * device tables, and captures one graph; *server is owned by the caller and
  * released with ppc_server_destroy.  PPC_EINVAL for bad arguments or a
  * field out of range (n_streams <= 64, max_batch <= 2^20, max_inflight <=
- * 2^24, tiles_per_item <= 2^20, reserved == 0), PPC_EDEVICE if no device
+ * 2^24, tiles_per_item <= 2^20), PPC_EDEVICE if no device
  * is current, PPC_ENOMEM if an allocation, a stream or the graph capture
  * fails (nothing is leaked). */
 ppc_status ppc_server_create(ppc_server **server, const void *pool, uint64_t pool_bytes, uint64_t column_bytes,
@@ -269,10 +271,19 @@ ppc_status ppc_server_create(ppc_server **server, const void *pool, uint64_t poo
  * poll and retry; PPC_EINVAL if it lies outside its column, the width is
  * bad, or it exceeds what one batch's item table holds: max(4096,
  * 16*max_batch)/4 items of 2^20 tiles of 16 KiB, at least 16 TiB) and makes
- * progress (retires finished batches, launches pending). */
+ * progress (retires finished batches, launches pending).
+ *
+ * Deadlines.  Every host wait of the server is a poll with a deadline: a
+ * batch still running `batch_timeout_us` after its launch turns the
+ * server's status into PPC_ETIMEDOUT (a failed batch into PPC_EDEVICE).
+ * From then on submit, poll and run_trace return that status and admit
+ * nothing; the batch itself stays in flight, so the only way on is
+ * ppc_server_destroy, which waits for the device. */
 ppc_status ppc_server_submit(ppc_server *server, const ppc_request *req);
 
-/* Makes progress and returns up to `cap` finished results in *out. */
+/* Makes progress and returns up to `cap` finished results in *out.
+ * Returns PPC_OK, or the server's error status (see Deadlines above);
+ * results finished before the error are still returned. */
 ppc_status ppc_server_poll(ppc_server *server, ppc_result *out, size_t cap, size_t *n_out);
 
 /* Snapshot of the server's counters (no progress is made).  PPC_EINVAL if
@@ -283,11 +294,15 @@ ppc_status ppc_server_get_stats(const ppc_server *server, ppc_server_stats *stat
  * start (non-decreasing); requests not admitted wait in arrival order.
  * results[i] receives request i's result (its tag is i) and *stats the
  * latency percentiles (arrival -> counts on host) and throughput.  The
- * server must be idle (nothing admitted, nothing unpolled). */
+ * server must be idle (nothing admitted, nothing unpolled).  Returns
+ * PPC_ETIMEDOUT or PPC_EDEVICE as soon as the server's status becomes one
+ * of them (see Deadlines above), so it never waits without bound. */
 ppc_status ppc_server_run_trace(ppc_server *server, const ppc_request *reqs, const uint64_t *arrival_ns, size_t n,
                                 ppc_result *results, ppc_trace_stats *stats);
 
-/* Waits for the server's streams, then frees it. */
+/* Waits for the server's streams, then frees it.  This is the one wait
+ * without a deadline: the device must be done with the server's buffers
+ * before they are freed. */
 ppc_status ppc_server_destroy(ppc_server *server);
 
 #ifdef __cplusplus

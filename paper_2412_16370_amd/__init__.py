@@ -18,7 +18,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libppc.so")
 
-PPC_OK, PPC_EINVAL, PPC_ENOMEM, PPC_EDEVICE, PPC_EBUSY = 0, 1, 2, 3, 4
+PPC_OK, PPC_EINVAL, PPC_ENOMEM, PPC_EDEVICE, PPC_EBUSY, PPC_ETIMEDOUT = 0, 1, 2, 3, 4, 5
 WIDTHS = (8, 16, 32, 64)
 
 
@@ -52,7 +52,7 @@ class ppc_server_cfg(ctypes.Structure):
     _fields_ = [("n_streams", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
                 ("max_inflight", ctypes.c_uint32), ("tiles_per_item", ctypes.c_uint32),
                 ("inflight_bytes", ctypes.c_uint64), ("waves", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("batch_timeout_us", ctypes.c_uint32)]
 
 
 class ppc_request(ctypes.Structure):

@@ -34,6 +34,7 @@ const char *ppc_status_string(int status) {
     case PPC_ENOMEM: return "PPC_ENOMEM: allocation failed";
     case PPC_EDEVICE: return "PPC_EDEVICE: HIP runtime or launch failure";
     case PPC_EBUSY: return "PPC_EBUSY: not admitted, retry later";
+    case PPC_ETIMEDOUT: return "PPC_ETIMEDOUT: a batch passed its deadline on the device";
     default: return "PPC_UNKNOWN";
     }
 }

@@ -20,9 +20,15 @@ ppc_status plain_pospopcnt(unsigned width, uint64_t *counts, const void *buf, si
 ppc_status plain_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf, size_t nbytes, uint64_t offset,
                               hipStream_t st, hipEvent_t ev_start, hipEvent_t ev_stop);
 
-// Wave cap of the plain call's grid on a device: the value set with
-// ppc_set_plain_geometry, else one 8-wave block on 3/4 of the CUs.
-unsigned plain_wave_cap(int device);
+// Launch geometry of the plain call on a device: the wave cap set with
+// ppc_set_plain_geometry, else one 8-wave block on 3/4 of the CUs, and the
+// waves per block.  Read once per call, so the pieces a long input is cut
+// into and the grids that count them use the same pair.
+struct PlainGeometry {
+    unsigned waves;
+    unsigned wpb;
+};
+PlainGeometry plain_geometry(int device);
 
 // The same override, else one 8-wave block on every CU (the grid of the
 // accumulation-schedule variants, whose extra ALU work wants every CU).

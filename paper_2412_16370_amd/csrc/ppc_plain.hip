@@ -138,8 +138,10 @@ __global__ __launch_bounds__(WPB *kWave) void read_roofline_kernel(const uint4 *
 }
 
 // ---- host side -----------------------------------------------------------
-static std::atomic<unsigned> g_plain_waves{0};        // 0 = default
-static std::atomic<unsigned> g_plain_wpb{8};
+// Launch geometry set by ppc_set_plain_geometry, packed into one word so a
+// call reads a consistent pair: low 32 bits = wave cap (0 = default), high
+// 32 bits = waves per block.
+static std::atomic<uint64_t> g_plain_geom{(uint64_t)8 << 32};
 
 // Launch events: when given, the start/stop events are recorded by the
 // kernel dispatch itself (hipExtLaunchKernel), so their interval is the
@@ -167,23 +169,25 @@ static hipError_t launch_plain(const PlainArgs &a, unsigned blocks, unsigned wpb
 // either, so a streaming CU wants its two waves per SIMD, and the
 // likeliest reading is that fewer requesting CUs contend less on the way
 // to the HBM while still keeping it busy.
-unsigned plain_wave_cap(int device) {
-    unsigned w = g_plain_waves.load(std::memory_order_relaxed);
-    if (w) return w;
-    return std::max(1u, (unsigned)device_cus(device) * 3u / 4u) * 8u;
+PlainGeometry plain_geometry(int device) {
+    const uint64_t g = g_plain_geom.load(std::memory_order_relaxed);
+    PlainGeometry geo{(unsigned)g, (unsigned)(g >> 32)};
+    if (geo.waves == 0) geo.waves = std::max(1u, (unsigned)device_cus(device) * 3u / 4u) * 8u;
+    return geo;
 }
 
 unsigned full_grid_wave_cap(int device) {
-    unsigned w = g_plain_waves.load(std::memory_order_relaxed);
+    const unsigned w = (unsigned)g_plain_geom.load(std::memory_order_relaxed);
     if (w) return w;
     return (unsigned)device_cus(device) * 8u;  // one 8-wave block per CU
 }
 
 // One launch over a range the caller has sized with kMaxTilesPerWave.
+// `geo` is the geometry the caller sized the range with: the grid holds
+// min(tiles, geo.waves) waves or more, so no wave gets more tiles than the
+// caller allowed for.
 static ppc_status plain_launch_range(unsigned width, uint64_t *counts, const uint8_t *buf, size_t nbytes,
-                                     uint32_t m, hipStream_t st, LaunchEvents ev) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
+                                     uint32_t m, PlainGeometry geo, hipStream_t st, LaunchEvents ev) {
     const uintptr_t b0 = (uintptr_t)buf;
     const uintptr_t b1 = b0 + nbytes;
     const uintptr_t f = (b0 + 15u) & ~(uintptr_t)15u;  // first full chunk
@@ -209,10 +213,9 @@ static ppc_status plain_launch_range(unsigned width, uint64_t *counts, const uin
     }
     a.n_full_tiles = (uint32_t)(a.n_chunks / kTileChunks);
     a.n_tiles = (uint32_t)((a.n_chunks + kTileChunks - 1) / kTileChunks);
-    const unsigned wpb = g_plain_wpb.load(std::memory_order_relaxed);
-    uint64_t waves = std::min<uint64_t>(std::max<uint32_t>(a.n_tiles, 1u), plain_wave_cap(dev));
-    const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
-    return launch_plain(a, blocks, wpb, st, ev) == hipSuccess ? PPC_OK : PPC_EDEVICE;
+    const uint64_t waves = std::min<uint64_t>(std::max<uint32_t>(a.n_tiles, 1u), geo.waves);
+    const unsigned blocks = (unsigned)((waves + geo.wpb - 1) / geo.wpb);
+    return launch_plain(a, blocks, geo.wpb, st, ev) == hipSuccess ? PPC_OK : PPC_EDEVICE;
 }
 
 // Per-wave counts are 32-bit: a wave adds at most 64 lanes x 2 dwords x 16
@@ -236,16 +239,16 @@ ppc_status plain_pospopcnt_at(unsigned width, uint64_t *counts, const void *buf,
     const uint32_t m = (uint32_t)(((uintptr_t)p - (uintptr_t)(offset % 8u) + 8u) % s);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
+    const PlainGeometry geo = plain_geometry(dev);  // one read: pieces and grids agree
     const size_t tile_bytes = (size_t)kTileChunks * 16u;
-    const size_t piece = std::min<size_t>(kMaxLaunchBytes,
-                                          (size_t)plain_wave_cap(dev) * kMaxTilesPerWave * tile_bytes);
+    const size_t piece = std::min<size_t>(kMaxLaunchBytes, (size_t)geo.waves * kMaxTilesPerWave * tile_bytes);
     size_t done = 0;
     while (done < nbytes) {  // pieces start at multiples of 8 from buf: same m
         const size_t len = std::min(piece, nbytes - done);
         LaunchEvents ev;  // start on the first launch, stop on the last
         if (done == 0) ev.start = ev_start;
         if (done + len == nbytes) ev.stop = ev_stop;
-        ppc_status rc = plain_launch_range(width, counts, p + done, len, m, st, ev);
+        ppc_status rc = plain_launch_range(width, counts, p + done, len, m, geo, st, ev);
         if (rc != PPC_OK) return rc;
         done += len;
     }
@@ -299,8 +302,7 @@ ppc_status ppc_popcount(uint64_t *total, const void *buf, size_t nbytes, void *s
 ppc_status ppc_set_plain_geometry(unsigned waves, unsigned waves_per_block) {
     if (!(waves_per_block == 2 || waves_per_block == 4 || waves_per_block == 8)) return PPC_EINVAL;
     if (waves > (1u << 24)) return PPC_EINVAL;
-    g_plain_waves.store(waves);
-    g_plain_wpb.store(waves_per_block);
+    g_plain_geom.store((uint64_t)waves | ((uint64_t)waves_per_block << 32));
     return PPC_OK;
 }
 
@@ -308,8 +310,9 @@ ppc_status ppc_get_plain_geometry(unsigned *waves, unsigned *waves_per_block) {
     if (!waves || !waves_per_block) return PPC_EINVAL;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return PPC_EDEVICE;
-    *waves = plain_wave_cap(dev);
-    *waves_per_block = g_plain_wpb.load();
+    const PlainGeometry geo = plain_geometry(dev);
+    *waves = geo.waves;
+    *waves_per_block = geo.wpb;
     return PPC_OK;
 }
 
@@ -324,8 +327,9 @@ ppc_status ppc_read_roofline_timed(uint64_t *sink, const void *buf, size_t nbyte
     const uint64_t n_tiles64 = nbytes / ((size_t)kTileChunks * 16u);
     if (n_tiles64 >= (1ull << 32)) return PPC_EINVAL;
     const uint32_t n_tiles = (uint32_t)n_tiles64;
-    const unsigned wpb = g_plain_wpb.load();
-    const uint64_t waves = std::min<uint64_t>(n_tiles, plain_wave_cap(dev));
+    const PlainGeometry geo = plain_geometry(dev);
+    const unsigned wpb = geo.wpb;
+    const uint64_t waves = std::min<uint64_t>(n_tiles, geo.waves);
     const unsigned blocks = (unsigned)((waves + wpb - 1) / wpb);
     hipStream_t st = (hipStream_t)stream;
     const uint4 *body = static_cast<const uint4 *>(buf);

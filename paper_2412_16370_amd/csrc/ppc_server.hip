@@ -54,6 +54,7 @@ struct Lane {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool busy = false;
+    uint64_t t_launch = 0;        // host time the batch in flight was launched
     bool failed = false;          // an enqueue of the batch in flight failed
     std::vector<uint32_t> slots;  // slot ids of the batch in flight
     // staging buffer: BatchHeader, ArrayInfo[max_batch], WorkItem[item_cap]
@@ -109,13 +110,19 @@ void server_free(ppc_server *s) {
 }
 
 // Retires finished batches: results move to the completed queue, slots and
-// in-flight bytes are released.
+// in-flight bytes are released.  A batch still running `batch_timeout_us` after its launch makes the
+// server's status PPC_ETIMEDOUT: the batch stays in flight (its buffers are
+// still the device's), and every later poll or trace returns that status.
 void retire(ppc_server *s) {
     const uint64_t t_begin = now_ns();
     for (auto &l : s->lanes) {
         if (!l.busy) continue;
         hipError_t q = hipEventQuery(l.done);
-        if (q == hipErrorNotReady) continue;
+        if (q == hipErrorNotReady) {
+            if (t_begin - l.t_launch > (uint64_t)s->cfg.batch_timeout_us * 1000u && s->sticky == PPC_OK)
+                s->sticky = PPC_ETIMEDOUT;
+            continue;
+        }
         if (l.failed) q = hipErrorUnknown;
         if (q != hipSuccess && s->sticky == PPC_OK) s->sticky = PPC_EDEVICE;
         const uint64_t t = now_ns();
@@ -184,6 +191,7 @@ void dispatch(ppc_server *s) {
         h->n_arrays = n;
         h->n_items = (uint32_t)items.size();
         h->n_groups = (uint32_t)groups.size() - 1u;
+        l.t_launch = now_ns();
         hipError_t e = hipGraphLaunch(l.exec, l.stream);
         if (e == hipSuccess) e = hipEventRecord(l.done, l.stream);
         if (e != hipSuccess) {
@@ -242,8 +250,8 @@ ppc_status ppc_server_create(ppc_server **out, const void *pool, uint64_t pool_b
     if (!pool || pool_bytes == 0 || column_bytes == 0 || pool_bytes % column_bytes != 0) return PPC_EINVAL;
     ppc_server_cfg c{};
     if (cfg) c = *cfg;
-    if (c.reserved != 0) return PPC_EINVAL;
     if (c.n_streams == 0) c.n_streams = 3;
+    if (c.batch_timeout_us == 0) c.batch_timeout_us = 10000000u;  // 10 s
     if (c.max_batch == 0) c.max_batch = 4096;
     if (c.max_inflight == 0) c.max_inflight = 16384;
     if (c.tiles_per_item == 0) c.tiles_per_item = 16;
@@ -304,6 +312,7 @@ ppc_status ppc_server_create(ppc_server **out, const void *pool, uint64_t pool_b
 
 ppc_status ppc_server_submit(ppc_server *s, const ppc_request *req) {
     if (!s) return PPC_EINVAL;
+    if (s->sticky != PPC_OK) return s->sticky;  // failed or timed out: no new work
     ppc_status rc = validate(s, req);
     if (rc != PPC_OK) return rc;
     rc = admit(s, req, now_ns());

@@ -43,9 +43,24 @@ def test_symbol_exported(lib, name):
 
 
 def test_status_strings(lib):
-    for code in range(5):
-        assert lib.ppc_status_string(code)
+    for code in range(6):
+        assert lib.ppc_status_string(code) != b"PPC_UNKNOWN"
+    assert lib.ppc_status_string(5).startswith(b"PPC_ETIMEDOUT")
     assert lib.ppc_status_string(99) == b"PPC_UNKNOWN"
+
+
+def test_struct_layouts_match_the_header():
+    """The binding's ctypes structs have the sizes and field offsets of the
+    C structs in include/ppc.h (natural alignment, no packing)."""
+    import paper_2412_16370_amd as ppc
+
+    assert ctypes.sizeof(ppc.ppc_desc) == 32
+    assert ctypes.sizeof(ppc.ppc_server_cfg) == 32
+    assert ppc.ppc_server_cfg.inflight_bytes.offset == 16
+    assert ppc.ppc_server_cfg.batch_timeout_us.offset == 28
+    assert ctypes.sizeof(ppc.ppc_request) == 32
+    assert ctypes.sizeof(ppc.ppc_result) == 32 + 64 * 8
+    assert ppc.PPC_ETIMEDOUT == 5
 
 
 def test_invalid_arguments_rejected_before_any_device_work(lib):

@@ -165,9 +165,10 @@ def test_autotuned_plan_replays_and_cache(ppc, tmp_path, monkeypatch):
 
 
 def test_ten_thousand_arrays_full_size(ppc, tmp_path, monkeypatch):
-    """10,000 arrays, log-uniform 16 B .. 16 MiB, mixed widths, p ~ U[0,1]:
-    batched == plain for every array; == oracle for every array up to 1 MiB
-    and a seeded 1% sample of the larger ones."""
+    """10,000 arrays, log-uniform 16 B .. 16 MiB, mixed widths, p ~ U[0,1]
+    (11.95 GB): every array's counts equal the oracle on its bytes (threads
+    over the host cores, one Fig. 2 loop per array) and what a plain call
+    adds for it."""
     monkeypatch.setenv("PPC_TUNE_CACHE", str(tmp_path / "tune.txt"))
     spec = synth.batch_spec(10_000, seed=3)
     pool = make_pool(spec, seed=3)
@@ -180,14 +181,11 @@ def test_ten_thousand_arrays_full_size(ppc, tmp_path, monkeypatch):
         ppc.ppc_plan_destroy(plan)
     got = ppc.counts_to_numpy(counts).reshape(10_000, 64)
     assert np.array_equal(got, plain_counts(ppc, pool, spec))
-    small = [i for i in range(10_000) if spec["lengths"][i] <= MiB]
-    big = [i for i in range(10_000) if spec["lengths"][i] > MiB]
-    sample = sorted(np.random.default_rng(99).choice(big, size=max(1, len(big) // 100), replace=False))
-    want = {}
-    for i in small + list(sample):
-        o, n, w = int(spec["offsets"][i]), int(spec["lengths"][i]), int(spec["widths"][i])
-        want[i] = oracle.pospopcnt(pool[o:o + n].cpu().numpy(), w)
-    check_rows(got, spec, want)
+    host = pool.cpu().numpy()
+    del pool
+    torch.cuda.empty_cache()
+    want = oracle.pospopcnt_ranges(host, spec["offsets"], spec["lengths"], spec["widths"])
+    check_rows(got, spec, dict(enumerate(want)))
 
 
 def test_empty_plan_and_bad_descriptors(ppc):

@@ -4,6 +4,8 @@ Each served request must equal, bit for bit, the oracle on its bytes, the
 plain call run alone on the same bytes, and the same request served alone
 (tolerance 0) -- whatever batch it shared on the device.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -57,14 +59,40 @@ def alone_plain(ppc, dev_pool, t, col_bytes=COL_BYTES):
     return ppc.counts_to_numpy(counts).reshape(n, 64)
 
 
+WAIT_S = 60.0  # no served request in these tests takes more than milliseconds
+
+
+def poll_until(ppc, server, n, cap=1024):
+    """Polls until n results have come back, failing the test (instead of
+    hanging the run) if they have not within WAIT_S seconds."""
+    out = []
+    deadline = time.monotonic() + WAIT_S
+    while len(out) < n:
+        out += ppc.ppc_server_poll(server, cap)
+        assert time.monotonic() < deadline, "only %d of %d results after %.0f s" % (len(out), n, WAIT_S)
+    return out
+
+
 def served_alone(ppc, server, t, i):
     assert ppc.ppc_server_submit(server, t["column"][i], t["width"][i], t["offset"][i], t["length"][i],
                                  tag=10**9 + i) == ppc.PPC_OK
-    while True:
-        res = ppc.ppc_server_poll(server)
-        if res:
-            assert len(res) == 1 and res[0].tag == 10**9 + i and res[0].status == 0
-            return np.array(res[0].counts[:res[0].width], dtype=np.uint64)
+    res = poll_until(ppc, server, 1)
+    assert len(res) == 1 and res[0].tag == 10**9 + i and res[0].status == 0
+    return np.array(res[0].counts[:res[0].width], dtype=np.uint64)
+
+
+def check_all_against_oracle(host_pool, t, results, col_bytes):
+    """Every served result equals the oracle on its bytes (threads over the
+    host cores, one Fig. 2 loop per request)."""
+    n = len(t["length"])
+    starts = [int(t["column"][i]) * col_bytes + int(t["offset"][i]) for i in range(n)]
+    want = oracle.pospopcnt_ranges(host_pool, starts, t["length"], t["width"])
+    for i in range(n):
+        r = results[i]
+        w = int(t["width"][i])
+        assert r.tag == i and r.status == 0 and r.width == w, "request %d" % i
+        assert np.array_equal(np.array(r.counts[:w], dtype=np.uint64), want[i]), "request %d" % i
+        assert not any(r.counts[w:]), "request %d" % i
 
 
 def test_trace_matches_oracle_plain_and_alone(ppc, pool):
@@ -118,7 +146,9 @@ def test_submit_poll_api(ppc, pool):
     got = {}
     try:
         i = 0
+        deadline = time.monotonic() + WAIT_S
         while i < 200 or len(got) < 200:
+            assert time.monotonic() < deadline, "stuck at %d submitted, %d done" % (i, len(got))
             if i < 200:
                 rc = ppc.ppc_server_submit(server, t["column"][i], t["width"][i], t["offset"][i],
                                            t["length"][i], tag=i)
@@ -144,8 +174,7 @@ def test_invalid_requests_rejected(ppc, pool):
                 ppc.ppc_server_submit(server, *bad)
             assert e.value.status == ppc.PPC_EINVAL
         assert ppc.ppc_server_submit(server, 0, 16, COL_BYTES - 5, 5) == ppc.PPC_OK
-        while not ppc.ppc_server_poll(server):
-            pass
+        assert len(poll_until(ppc, server, 1)) == 1
     finally:
         ppc.ppc_server_destroy(server)
 
@@ -173,46 +202,75 @@ def test_onehot_u32_columns_count_the_histogram(ppc):
         ppc.ppc_server_destroy(server)
 
 
-def test_full_size_pool_at_half_load(ppc):
-    """The serving workload at full size, in the default server
-    configuration the bench times: a 1 GiB pool of one-hot uint32 columns
-    (16 x 64 MiB, 32 categories, Zipf s = 1.0) and 20,000 Poisson requests
-    (64 B .. 64 MiB, unaligned) offered at about half the plain kernel's
-    bandwidth.  Every result equals the plain call on the same bytes, a
-    seeded sample equals the oracle, and sampled requests served alone
-    equal their result in the mix (tolerance 0)."""
-    col = 64 * MiB
-    n = 20_000
-    pool = synth.device_onehot_u32_columns(16, col // 4, seed=4, device="cuda:0")
+@pytest.fixture(scope="module")
+def full_pool(ppc):
+    """The serving pool at full size: 1 GiB of one-hot uint32 columns (16 x
+    64 MiB, 32 categories, Zipf s = 1.0), on the device and copied to host."""
+    pool = synth.device_onehot_u32_columns(16, FULL_COL // 4, seed=4, device="cuda:0")
     torch.cuda.synchronize()
-    rate = 0.5 * 6.5e12 / synth.log_uniform_mean(64, 64 * MiB)
-    t = synth.serve_trace(n, seed=4, n_columns=16, column_bytes=col, rate_per_s=rate, lo=64, hi=64 * MiB)
-    server = ppc.ppc_server_create(pool, column_bytes=col)
+    return pool, pool.cpu().numpy()
+
+
+FULL_COL = 64 * MiB
+
+
+def full_trace(n, rho, seed):
+    """Poisson requests (64 B .. 64 MiB, unaligned) over the full pool,
+    offered at rho times 6.5 TB/s, about the plain kernel's bandwidth."""
+    rate = rho * 6.5e12 / synth.log_uniform_mean(64, 64 * MiB)
+    return synth.serve_trace(n, seed=seed, n_columns=16, column_bytes=FULL_COL, rate_per_s=rate, lo=64,
+                             hi=64 * MiB)
+
+
+def test_full_size_pool_at_half_load(ppc, full_pool):
+    """The serving workload at full size, in the default server
+    configuration the bench times, at half load: 20,000 Poisson requests.
+    Every result equals the oracle on its bytes and the plain call on the
+    same bytes, and sampled requests served alone equal their result in
+    the mix (tolerance 0)."""
+    pool, host = full_pool
+    n = 20_000
+    t = full_trace(n, 0.5, seed=4)
+    server = ppc.ppc_server_create(pool, column_bytes=FULL_COL)
     try:
         results, stats = ppc.ppc_server_run_trace(server, t["column"], t["width"], t["offset"], t["length"],
                                                   t["arrival_ns"])
         assert stats["n_requests"] == n and stats["mean_batch"] > 1.0
-        plain = alone_plain(ppc, pool, t, col_bytes=col)
+        check_all_against_oracle(host, t, results, FULL_COL)
+        plain = alone_plain(ppc, pool, t, col_bytes=FULL_COL)
         for i in range(n):
-            r = results[i]
             w = int(t["width"][i])
-            assert r.tag == i and r.status == 0 and r.width == w
-            assert np.array_equal(np.array(r.counts[:w], dtype=np.uint64), plain[i, :w]), "request %d" % i
+            assert np.array_equal(np.array(results[i].counts[:w], dtype=np.uint64), plain[i, :w]), i
         rng = np.random.default_rng(7)
-        for i in rng.choice(n, size=60, replace=False):
-            i = int(i)
-            base = int(t["column"][i]) * col + int(t["offset"][i])
-            host = pool[base:base + int(t["length"][i])].cpu().numpy()
-            w = int(t["width"][i])
-            assert np.array_equal(np.array(results[i].counts[:w], dtype=np.uint64), oracle.pospopcnt(host, w))
+        t_one = {k: t[k] for k in ("column", "width", "offset", "length")}
         for i in rng.choice(n, size=20, replace=False):
             i = int(i)
             w = int(t["width"][i])
             got = np.array(results[i].counts[:w], dtype=np.uint64)
-            t_one = {k: t[k] for k in ("column", "width", "offset", "length")}
             assert np.array_equal(served_alone(ppc, server, t_one, i), got)
     finally:
         ppc.ppc_server_destroy(server)
+
+
+def test_full_size_pool_near_saturation(ppc, full_pool):
+    """The bench's second served configuration: the default server at 0.9
+    of the plain kernel's bandwidth, where batches run to hundreds of
+    requests and three streams overlap on the device.  Every one of 20,000
+    results equals the oracle on its bytes."""
+    pool, host = full_pool
+    n = 20_000
+    t = full_trace(n, 0.9, seed=5)
+    server = ppc.ppc_server_create(pool, column_bytes=FULL_COL)
+    try:
+        results, stats = ppc.ppc_server_run_trace(server, t["column"], t["width"], t["offset"], t["length"],
+                                                  t["arrival_ns"])
+        big = ppc.ppc_server_get_stats(server)["max_batch_seen"]
+    finally:
+        ppc.ppc_server_destroy(server)
+    print("rho 0.9: mean batch %.1f, largest %d, p50 %.0f us, p99 %.0f us"
+          % (stats["mean_batch"], big, stats["p50_ns"] / 1e3, stats["p99_ns"] / 1e3))
+    assert stats["n_requests"] == n and big >= 64
+    check_all_against_oracle(host, t, results, FULL_COL)
 
 
 def test_edge_requests_in_one_batch(ppc, pool):
@@ -238,5 +296,79 @@ def test_edge_requests_in_one_batch(ppc, pool):
             want = oracle.pospopcnt(host[c * COL_BYTES + o:c * COL_BYTES + o + n], w)
             assert np.array_equal(np.array(r.counts[:w], dtype=np.uint64), want), (c, w, o, n)
             assert not any(r.counts[w:])
+    finally:
+        ppc.ppc_server_destroy(server)
+
+
+def test_burst_fills_every_batch_to_max_batch(ppc, pool):
+    """640 requests arriving at once on a server of two streams with
+    max_batch = 64: every batch goes out full, exactly 64 requests, ten
+    batches in all, and every result equals the oracle."""
+    host, dev_pool = pool
+    t = trace(640, seed=44, rate=1e6)
+    t["arrival_ns"] = np.zeros(640, dtype=np.int64)
+    server = ppc.ppc_server_create(dev_pool, column_bytes=COL_BYTES, cfg=ppc.ppc_server_cfg(2, 64, 0, 0, 0, 0, 0))
+    try:
+        results, stats = ppc.ppc_server_run_trace(server, t["column"], t["width"], t["offset"], t["length"],
+                                                  t["arrival_ns"])
+        assert ppc.ppc_server_get_stats(server)["max_batch_seen"] == 64
+    finally:
+        ppc.ppc_server_destroy(server)
+    assert stats["batches"] == 10 and stats["mean_batch"] == 64.0
+    check_all_against_oracle(host, t, results, COL_BYTES)
+
+
+def test_item_table_cap_and_tile_doubling(ppc):
+    """A server whose item table (4096 items) cannot take a batch's worth of
+    large requests at one tile per item.  A request of 2048 tiles would need
+    2048 items, more than a quarter of the table, so its tiles per item
+    double to 2 (1024 items), and the fifth such request of a batch no
+    longer fits, so the batch closes at four although max_batch is 8.  Ten
+    requests arriving at once therefore go out as 4 + 4 + 2 (without the
+    doubling they would go 2 by 2, without the cap 8 + 2).  Then a mix of
+    large and small requests on the same server.  Every result equals the
+    oracle."""
+    col = 32 * MiB
+    host = synth.random_bytes(4 * col, seed=45)
+    dev_pool = torch.from_numpy(host).to("cuda:0")
+    big = dict(column=np.array([k % 4 for k in range(10)]), width=np.array([8, 16, 32, 64, 16] * 2),
+               offset=np.array([3, 0, 5, 1, 0, 7, 2, 9, 4, 6]),
+               arrival_ns=np.zeros(10, dtype=np.int64))
+    big["length"] = col - big["offset"]  # 2048 tiles of 16 KiB, the last one partial
+    cfg = ppc.ppc_server_cfg(1, 8, 0, 1, 0, 0, 0)  # one stream, 8 per batch, 1 tile per item
+    server = ppc.ppc_server_create(dev_pool, column_bytes=col, cfg=cfg)
+    try:
+        results, stats = ppc.ppc_server_run_trace(server, big["column"], big["width"], big["offset"],
+                                                  big["length"], big["arrival_ns"])
+        assert ppc.ppc_server_get_stats(server)["max_batch_seen"] == 4
+        assert stats["batches"] == 3
+        check_all_against_oracle(host, big, results, col)
+        mix = synth.serve_trace(300, seed=46, n_columns=4, column_bytes=col, rate_per_s=2e5, lo=1, hi=col)
+        results, stats = ppc.ppc_server_run_trace(server, mix["column"], mix["width"], mix["offset"],
+                                                  mix["length"], mix["arrival_ns"])
+        check_all_against_oracle(host, mix, results, col)
+    finally:
+        ppc.ppc_server_destroy(server)
+
+
+def test_batch_deadline_turns_into_timeout_status(ppc, pool):
+    """A deadline shorter than any batch (1 us from launch): the first batch
+    (800 MiB, far more than 1 us of device time) is still running when the
+    host next looks, so the trace returns PPC_ETIMEDOUT instead of waiting,
+    and the server then refuses new work.  The kernels themselves run to
+    their normal end; destroy waits for them."""
+    _, dev_pool = pool
+    n = 200
+    t = dict(column=np.arange(n) % N_COL, width=np.full(n, 16), offset=np.zeros(n, dtype=np.int64),
+             length=np.full(n, COL_BYTES), arrival_ns=np.zeros(n, dtype=np.int64))
+    cfg = ppc.ppc_server_cfg(1, 0, 0, 0, 0, 0, 1)
+    server = ppc.ppc_server_create(dev_pool, column_bytes=COL_BYTES, cfg=cfg)
+    try:
+        with pytest.raises(ppc.PpcError) as e:
+            ppc.ppc_server_run_trace(server, t["column"], t["width"], t["offset"], t["length"], t["arrival_ns"])
+        assert e.value.status == ppc.PPC_ETIMEDOUT
+        with pytest.raises(ppc.PpcError) as e:
+            ppc.ppc_server_submit(server, 0, 16, 0, 64)
+        assert e.value.status == ppc.PPC_ETIMEDOUT
     finally:
         ppc.ppc_server_destroy(server)
