@@ -195,6 +195,33 @@ ppc_status ppc_plan_get_info(const ppc_plan *plan, ppc_plan_info *info);
 ppc_status ppc_plan_destroy(ppc_plan *plan);
 
 /* ------------------------------------------------------------------------
+ * Batched count that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Each array's counts are exactly what
+ * the plain call (and a plan over the same descriptors) adds.
+ *
+ * `descs` is a DEVICE array of `n` ppc_desc (8-byte aligned), read by the
+ * kernels when the stream reaches the call; the buffers and counters it
+ * points to follow the plain call's rules.  n <= PPC_NOALLOC_MAX_ARRAYS,
+ * else PPC_EINVAL (nothing enqueued).  If any descriptor is invalid (bad
+ * width, NULL or misaligned counters, NULL buf with nbytes > 0, reserved
+ * != 0) nothing is counted, and if `n_invalid` (device, one uint32,
+ * optional) is given the kernels write there the number of invalid
+ * descriptors (0 when the batch was counted).
+ *
+ * Memory.  Every table the kernels use (array table, work items, work
+ * cursor) lives in one static device array of PPC_NOALLOC_SCRATCH_BYTES
+ * (8 MiB) per GPU, held until the process ends; the call enqueues two
+ * kernels and no copy, and calls no allocating routine.  Calls that
+ * overlap on one GPU (other streams, other host threads) share that array
+ * and race: order them on one stream.  PPC_EDEVICE if a launch fails.
+ * ---------------------------------------------------------------------- */
+#define PPC_NOALLOC_MAX_ARRAYS 65536u
+#define PPC_NOALLOC_SCRATCH_BYTES (256u + 64u * 65536u + 16u * 262144u)
+
+ppc_status ppc_batch_noalloc(const ppc_desc *descs, uint32_t n, uint32_t *n_invalid, void *stream);
+
+/* ------------------------------------------------------------------------
  * Serving form: count queries over device-resident columns.  A pool of
  * equal columns (pool_bytes = n_columns * column_bytes, device memory owned
  * by the caller) is counted by requests (column, width, offset, nbytes).

@@ -107,6 +107,7 @@ def _declare(lib):
         "ppc_plan_run": ([_c_ptr, _c_ptr], ctypes.c_int),
         "ppc_plan_get_info": ([_c_ptr, ctypes.POINTER(ppc_plan_info)], ctypes.c_int),
         "ppc_plan_destroy": ([_c_ptr], ctypes.c_int),
+        "ppc_batch_noalloc": ([_c_ptr, ctypes.c_uint32, _c_ptr, _c_ptr], ctypes.c_int),
         "ppc_server_create": ([ctypes.POINTER(_c_ptr), _c_ptr, ctypes.c_uint64, ctypes.c_uint64,
                                ctypes.POINTER(ppc_server_cfg)], ctypes.c_int),
         "ppc_server_submit": ([_c_ptr, ctypes.POINTER(ppc_request)], ctypes.c_int),
@@ -352,6 +353,20 @@ def ppc_plan_get_info(plan) -> dict:
 
 def ppc_plan_destroy(plan):
     _check(lib().ppc_plan_destroy(plan), "ppc_plan_destroy")
+
+
+def descs_bytes(descs) -> bytes:
+    """The raw bytes of a ctypes ppc_desc array (the C layout), to be placed
+    in device memory for :func:`ppc_batch_noalloc`."""
+    return ctypes.string_at(ctypes.addressof(descs), ctypes.sizeof(descs)) if len(descs) else b""
+
+
+def ppc_batch_noalloc(descs_dev, n, n_invalid=None, stream=None):
+    """``descs_dev``: device tensor (or address) holding ``n`` ppc_desc in
+    the C layout (see descs_bytes); ``n_invalid``: optional device tensor
+    of one 32-bit integer that receives the number of invalid descriptors."""
+    _check(lib().ppc_batch_noalloc(_ptr(descs_dev), int(n), _ptr(n_invalid), _stream(stream)),
+           "ppc_batch_noalloc")
 
 
 def ppc_server_create(pool, pool_bytes=None, column_bytes=None, cfg=None):

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "ppc.h"
+#include "ppc_device.hpp"
 
 namespace ppc {
 
@@ -44,8 +45,62 @@ static_assert(sizeof(BatchHeader) == 64, "BatchHeader layout");
 // Per-item tile cap: keeps every per-wave 32-bit count below 2^31.
 constexpr uint32_t kMaxItemTiles = 1u << 20;
 
-// Fills `ai` for one array.  Returns false for an invalid array.
-bool make_array_info(ArrayInfo &ai, const void *buf, uint64_t nbytes, uint64_t *counts, uint32_t width);
+// Fills `ai` for one array (host or device code).  Returns false for an
+// invalid array (same rules as the plain call); `ai` then describes an
+// empty array.
+__host__ __device__ inline bool make_array_info(ArrayInfo &ai, const void *buf, uint64_t nbytes, uint64_t *counts,
+                                                uint32_t width) {
+    ai = ArrayInfo{};
+    if (!(width == 8 || width == 16 || width == 32 || width == 64)) return false;
+    if (counts == nullptr || ((uintptr_t)counts & 7u) != 0) return false;
+    if (nbytes > 0 && buf == nullptr) return false;
+    if (nbytes == 0) {
+        ai.counts = reinterpret_cast<unsigned long long *>(counts);
+        ai.width = width;
+        return true;
+    }
+    const uintptr_t b0 = (uintptr_t)buf, b1 = b0 + nbytes;
+    const uintptr_t f = (b0 + 15u) & ~(uintptr_t)15u, e = b1 & ~(uintptr_t)15u;
+    if (f < e) {
+        const uint64_t n_chunks = (uint64_t)(e - f) / 16u;
+        const uint64_t n_tiles = (n_chunks + kTileChunks - 1) / kTileChunks;
+        if (n_tiles >= (1ull << 32)) return false;  // > 64 TiB in one array
+        ai.body = reinterpret_cast<const uint4 *>(f);
+        ai.n_chunks = n_chunks;
+        ai.n_full = (uint32_t)(n_chunks / kTileChunks);
+        ai.n_tiles = (uint32_t)n_tiles;
+        ai.edge0 = static_cast<const uint8_t *>(buf);
+        ai.edge0_len = (uint32_t)(f - b0);
+        ai.edge1 = reinterpret_cast<const uint8_t *>(e);
+        ai.edge1_len = (uint32_t)(b1 - e);
+    } else {
+        ai.edge0 = static_cast<const uint8_t *>(buf);
+        ai.edge0_len = (uint32_t)nbytes;  // <= 30
+    }
+    ai.counts = reinterpret_cast<unsigned long long *>(counts);
+    ai.width = width;
+    ai.m = (uint32_t)((uintptr_t)buf % (width / 8u));
+    return true;
+}
+
+// One work item on one wave: the item's tiles (and the array's head/tail
+// bytes if flagged) are counted and folded into the array's counters.
+__device__ __forceinline__ void run_item(const ArrayInfo *__restrict__ arrays, const WorkItem &it) {
+    const uint32_t lane = __lane_id();
+    const ArrayInfo ai = arrays[it.array];
+    const bool has_edge = (it.flags & 1u) != 0u;
+    uint4 edge = zero4();
+    if (has_edge) {
+        if (lane < 32) {
+            if (lane < ai.edge0_len) edge = byte_as_chunk((uint64_t)(ai.edge0 + lane), ai.edge0[lane]);
+        } else if (lane - 32 < ai.edge1_len) {
+            edge = byte_as_chunk((uint64_t)(ai.edge1 + (lane - 32)), ai.edge1[lane - 32]);
+        }
+    }
+    const uint32_t acc =
+        wave_count_tiles(ai.body, ai.n_chunks, ai.n_full, it.tile0, it.tile1, 1u, edge, has_edge);
+    fold_add(acc, ai.width, ai.m, ai.counts);
+}
 
 // Appends the work items of array `idx` (tiles split into pieces of at most
 // `tiles_per_item`).

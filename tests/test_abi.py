@@ -106,6 +106,15 @@ def test_stream_and_popcount_validation(lib):
     assert lib.ppc_popcount(fake, None, 0, None) == 0
 
 
+def test_noalloc_batch_validation(lib):
+    # checked before any HIP call: too many arrays, NULL or misaligned tables
+    assert lib.ppc_batch_noalloc(None, 65537, None, None) == 1
+    assert lib.ppc_batch_noalloc(0x1000, 65537, None, None) == 1
+    assert lib.ppc_batch_noalloc(None, 3, None, None) == 1
+    assert lib.ppc_batch_noalloc(0x1004, 3, None, None) == 1
+    assert lib.ppc_batch_noalloc(0x1000, 3, 0x1002, None) == 1
+
+
 def test_binding_bounds_nbytes_by_the_tensor():
     """The binding refuses a byte count larger than the tensor it is given,
     so a length mistake cannot turn into a read past the buffer."""

@@ -1,0 +1,148 @@
+"""GPU parity of the allocation-free batched call (ppc_batch_noalloc).
+
+Its output must equal, bit for bit, what a plan (ppc_plan_create +
+ppc_plan_run, the batched entry point that allocates) adds for the same
+descriptors, and the oracle's counts.  Two calls in a row share the
+library's static scratch array; the second is smaller, so a table entry or
+cursor left over from the first would show up in its counts.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MiB = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def ppc():
+    import paper_2412_16370_amd as ppc
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ppc.lib()
+    return ppc
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def make_pool(spec, seed):
+    pool = torch.full((spec["pool_bytes"] + 128,), 0xFF, dtype=torch.uint8, device=dev())
+    for i, (off, n, p) in enumerate(zip(spec["offsets"], spec["lengths"], spec["p"])):
+        if n:
+            synth.device_bernoulli(int(n), float(p), seed=seed * 1_000_003 + i, device=dev(),
+                                   out=pool[int(off):int(off) + int(n)])
+    torch.cuda.synchronize()
+    return pool
+
+
+def descs_for(ppc, pool, spec, counts):
+    n = len(spec["lengths"])
+    base, cbase = pool.data_ptr(), counts.data_ptr()
+    return ppc.make_descs([base + int(o) for o in spec["offsets"]], spec["lengths"],
+                          [cbase + i * 512 for i in range(n)], spec["widths"])
+
+
+def to_device(ppc, descs):
+    raw = ppc.descs_bytes(descs)
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev())
+
+
+def noalloc_counts(ppc, pool, spec):
+    n = len(spec["lengths"])
+    counts = torch.zeros((n, 64), dtype=torch.int64, device=dev())
+    descs_dev = to_device(ppc, descs_for(ppc, pool, spec, counts))
+    bad = torch.full((1,), 12345, dtype=torch.int32, device=dev())
+    print("noalloc call: %d arrays, %d bytes" % (n, int(spec["lengths"].sum())), flush=True)
+    ppc.ppc_batch_noalloc(descs_dev, n, bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    return ppc.counts_to_numpy(counts).reshape(n, 64)
+
+
+def plan_counts(ppc, pool, spec):
+    n = len(spec["lengths"])
+    counts = torch.zeros((n, 64), dtype=torch.int64, device=dev())
+    plan = ppc.ppc_plan_create(descs_for(ppc, pool, spec, counts), n,
+                               ppc.ppc_plan_opts(16, 0, 0, 0, 0))
+    try:
+        ppc.ppc_plan_run(plan)
+        torch.cuda.synchronize()
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    return ppc.counts_to_numpy(counts).reshape(n, 64)
+
+
+def check_against_oracle(got, pool, spec):
+    want = oracle.pospopcnt_ranges(pool.cpu().numpy(), spec["offsets"], spec["lengths"], spec["widths"])
+    for i, row in enumerate(want):
+        w = int(spec["widths"][i])
+        assert np.array_equal(got[i, :w], row), "array %d (w=%d, n=%d)" % (i, w, int(spec["lengths"][i]))
+        assert not got[i, w:].any()
+
+
+def test_two_calls_in_a_row_match_the_plan_and_the_oracle(ppc):
+    # first call: 2,500 arrays up to 8 MiB (whole 1 MiB items and shorter
+    # ones), unaligned starts; second call: 400 arrays up to 64 KiB
+    spec1 = synth.batch_spec(2500, seed=40, lo=16, hi=8 * MiB, start_jitter=64)
+    spec2 = synth.batch_spec(400, seed=41, lo=16, hi=64 * 1024, start_jitter=64)
+    pool1, pool2 = make_pool(spec1, seed=40), make_pool(spec2, seed=41)
+    got1 = noalloc_counts(ppc, pool1, spec1)
+    got2 = noalloc_counts(ppc, pool2, spec2)
+    assert np.array_equal(got1, plan_counts(ppc, pool1, spec1))
+    assert np.array_equal(got2, plan_counts(ppc, pool2, spec2))
+    check_against_oracle(got1, pool1, spec1)
+    check_against_oracle(got2, pool2, spec2)
+
+
+def test_edge_only_empty_and_single_arrays(ppc):
+    # every length 0..40 at start offsets 0..15, all widths, then one array
+    offs, lens, widths = [], [], []
+    pos = 0
+    for w in (8, 16, 32, 64):
+        for o in range(16):
+            for n in range(41):
+                offs.append(pos + o)
+                lens.append(n)
+                widths.append(w)
+                pos += 128
+    spec = dict(offsets=np.array(offs), lengths=np.array(lens), widths=np.array(widths),
+                p=np.full(len(lens), 0.5), pool_bytes=pos + 128)
+    pool = make_pool(spec, seed=42)
+    got = noalloc_counts(ppc, pool, spec)
+    assert np.array_equal(got, plan_counts(ppc, pool, spec))
+    check_against_oracle(got, pool, spec)
+    one = dict(offsets=np.array([3]), lengths=np.array([5 * MiB + 7]), widths=np.array([32]),
+               p=np.array([0.3]), pool_bytes=5 * MiB + 64)
+    pool1 = make_pool(one, seed=43)
+    got1 = noalloc_counts(ppc, pool1, one)
+    check_against_oracle(got1, pool1, one)
+
+
+def test_invalid_descriptor_counts_nothing_and_next_call_is_clean(ppc):
+    spec = synth.batch_spec(50, seed=44, lo=16, hi=256 * 1024)
+    pool = make_pool(spec, seed=44)
+    counts = torch.zeros((50, 64), dtype=torch.int64, device=dev())
+    descs = descs_for(ppc, pool, spec, counts)
+    descs[7].width = 12
+    descs[9].counts = counts.data_ptr() + 4
+    bad = torch.zeros(1, dtype=torch.int32, device=dev())
+    ppc.ppc_batch_noalloc(to_device(ppc, descs), 50, bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 2
+    assert not counts.any()
+    # an empty batch reports no invalid descriptor
+    ppc.ppc_batch_noalloc(None, 0, bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    # the same arrays, valid now, after the rejected call
+    got = noalloc_counts(ppc, pool, spec)
+    check_against_oracle(got, pool, spec)
+    with pytest.raises(ppc.PpcError):
+        ppc.ppc_batch_noalloc(to_device(ppc, descs), 65537, None)
