@@ -9,9 +9,11 @@ the timed region starts.
 
 Printed: one JSON line with the whole-job throughput (GB/s, 1 GB = 1e9 B),
 the roofline object of the dominant kernel (achieved bytes/s from HIP events
-around every timed launch, against the 8 TB/s HBM peak), the read-only
-roofline kernel on the same buffers, density variants, the batched and the
-served forms, and the CPU oracle timed on this host as a reported baseline.
+on the launch stream around back-to-back launches, and from events each
+launch's own dispatch records on an idle queue, against the 8 TB/s HBM
+peak), the read-only roofline kernel on the same buffers, every width at
+three bit densities, the batched and the served forms, and the CPU oracle
+timed on this host as a reported baseline.
 """
 from __future__ import annotations
 
@@ -94,47 +96,78 @@ def dispatch_timed(fn, bufs, reps, torch):
     return [a.elapsed_ms(b) for a, b in ev]
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The oracle on this host: multithreaded word loop over a bounded
-    sample of the same workload (256 MiB of Bernoulli(0.5) bytes at each
-    width, as many passes as fit the time target)."""
+def cpu_model() -> str:
+    """The host CPU's model name as lscpu reports it, with its family, model
+    and stepping numbers (and its BIOS name too when the two differ), else
+    /proc/cpuinfo's."""
+    import subprocess
+
+    names, ids = [], {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            key, _, val = line.partition(":")
+            key, val = key.strip(), val.strip()
+            if key in ("Model name", "BIOS Model name") and val and val not in names:
+                names.append(val)
+            if key in ("CPU family", "Model", "Stepping") and val:
+                ids.setdefault(key, val)
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if names and ids:
+        names[0] += " (family %s, model %s, stepping %s)" % (
+            ids.get("CPU family", "?"), ids.get("Model", "?"), ids.get("Stepping", "?"))
+    if not names:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        names.append(line.split(":", 1)[1].strip())
+                        break
+        except OSError:
+            pass
+    return " / ".join(names) or "unknown"
+
+
+def cpu_baseline(runs=10):
+    """The oracle on this host: the Fig. 2 word loop over the config-2 input
+    (one 256 MiB array of Bernoulli(0.5) bytes) at every width, single-
+    threaded and on every core this process may use (split at word
+    boundaries), and over the config-1 input (2 MiB, w = 16); each figure is
+    the median of `runs` timed runs."""
     import oracle
     import synth
 
-    threads = min(16, os.cpu_count() or 1)
-    sample = synth.random_bytes(64 * MiB, seed=0)
-    done = 0
-    t0 = time.perf_counter()
-    while True:
-        for w in WIDTHS:
-            oracle.pospopcnt_mt(sample, w, threads)
-            done += sample.size
-        if time.perf_counter() - t0 > seconds_target / 2:
-            break
-    mt = done / (time.perf_counter() - t0) / 1e9
-    t0 = time.perf_counter()
-    oracle.pospopcnt(sample[: 16 * MiB], 16)
-    st = 16 * MiB / (time.perf_counter() - t0) / 1e9
+    threads = oracle.host_threads()
+
+    def med_gbps(fn, nbytes):
+        t = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            fn()
+            t.append(time.perf_counter() - t0)
+        t.sort()
+        return {"median": round(nbytes / t[len(t) // 2] / 1e9, 4), "min": round(nbytes / t[-1] / 1e9, 4),
+                "max": round(nbytes / t[0] / 1e9, 4)}
+
+    t_start = time.perf_counter()
+    sample = synth.random_bytes(CALL_BYTES, seed=10)
+    per_width = {}
+    for w in WIDTHS:
+        per_width[str(w)] = {"single_thread_GBps": med_gbps(lambda: oracle.pospopcnt(sample, w), CALL_BYTES),
+                             "all_cores_GBps": med_gbps(lambda: oracle.pospopcnt_mt(sample, w, threads),
+                                                        CALL_BYTES)}
     cfg1 = synth.random_bytes(2 * MiB, seed=0)
-    t0 = time.perf_counter()
-    for _ in range(8):
-        oracle.pospopcnt(cfg1, 16)
-    st_cfg1 = 8 * 2 * MiB / (time.perf_counter() - t0) / 1e9
-    model = "unknown"
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
-    return {"value": round(mt, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": "%d MiB passes of 64 MiB random bytes over w=8,16,32,64 "
-                      "(multithreaded word loop, split at word boundaries)" % (done // MiB),
-            "single_thread_GBps": round(st, 4),
-            "config1_2MiB_w16_single_thread_GBps": round(st_cfg1, 4),
-            "cpu_model": model, "host_cpus_visible": os.cpu_count()}
+    config1 = {"single_thread_GBps": med_gbps(lambda: oracle.pospopcnt(cfg1, 16), 2 * MiB),
+               "all_cores_GBps": med_gbps(lambda: oracle.pospopcnt_mt(cfg1, 16, threads), 2 * MiB)}
+    mt = sorted(v["all_cores_GBps"]["median"] for v in per_width.values())
+    return {"value": round(sum(mt) / len(mt), 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
+            "sample": "one 256 MiB array of random bytes at w = 8, 16, 32, 64 (the config-2 input at p = 0.5), "
+                      "%d timed runs per width and thread count; value = mean over widths of the all-core "
+                      "medians" % runs,
+            "per_width_256MiB": per_width, "config1_2MiB_w16": config1,
+            "cpu_model": cpu_model(), "host_cpus_visible": os.cpu_count(),
+            "seconds": round(time.perf_counter() - t_start, 1)}
 
 
 def batched_leg(ppc, torch, synth, dev, reps):
@@ -204,25 +237,42 @@ def served_leg(ppc, torch, synth, dev, plain_gbps, n_requests=100_000, rho=0.5):
                           lo=64, hi=64 * MiB)
     out = {"n_requests": n_requests, "offered_load": rho, "offered_req_per_s": round(rate),
            "offered_GBps": round(rho * plain_gbps, 1)}
-    for name, cfg in (("continuous", None),
-                      ("one_at_a_time", ppc.ppc_server_cfg(1, 1, 0, 0, 0, 0, 0))):
+    one = ppc.ppc_server_cfg(1, 1, 0, 0, 0, 0, 0)  # one stream, one request per batch
+
+    def run(name, cfg, trace, k):
         server = ppc.ppc_server_create(pool, column_bytes=col_bytes, cfg=cfg)
         try:
-            k = n_requests if name == "continuous" else min(n_requests, 20_000)
-            _, st = ppc.ppc_server_run_trace(server, t["column"][:k], t["width"][:k], t["offset"][:k],
-                                             t["length"][:k], t["arrival_ns"][:k])
+            _, st = ppc.ppc_server_run_trace(server, trace["column"][:k], trace["width"][:k], trace["offset"][:k],
+                                             trace["length"][:k], trace["arrival_ns"][:k])
         finally:
             ppc.ppc_server_destroy(server)
-        out[name] = {"requests": k, "p50_us": round(st["p50_ns"] / 1e3, 1),
-                     "p99_us": round(st["p99_ns"] / 1e3, 1), "mean_us": round(st["mean_ns"] / 1e3, 1),
-                     "max_us": round(st["max_ns"] / 1e3, 1), "GBps": round(st["gbps"], 1),
-                     "batches": st["batches"], "mean_batch": round(st["mean_batch"], 2),
-                     "busy_rejections": st["busy_rejections"],
-                     "host_dispatch_ms": round(st["host_dispatch_ns"] / 1e6, 2),
-                     "host_retire_ms": round(st["host_retire_ns"] / 1e6, 2),
-                     "makespan_ms": round(st["makespan_ns"] / 1e6, 2)}
         log("served %s: p50 %.1f us p99 %.1f us, %.1f GB/s, mean batch %.1f" % (
             name, st["p50_ns"] / 1e3, st["p99_ns"] / 1e3, st["gbps"], st["mean_batch"]))
+        return {"requests": k, "p50_us": round(st["p50_ns"] / 1e3, 1),
+                "p99_us": round(st["p99_ns"] / 1e3, 1), "mean_us": round(st["mean_ns"] / 1e3, 1),
+                "max_us": round(st["max_ns"] / 1e3, 1), "GBps": round(st["gbps"], 1),
+                "batches": st["batches"], "mean_batch": round(st["mean_batch"], 2),
+                "busy_rejections": st["busy_rejections"],
+                "host_dispatch_ms": round(st["host_dispatch_ns"] / 1e6, 2),
+                "host_retire_ms": round(st["host_retire_ns"] / 1e6, 2),
+                "makespan_ms": round(st["makespan_ns"] / 1e6, 2)}
+
+    out["continuous"] = run("continuous", None, t, n_requests)
+    # one request at a time at the same offered load: it cannot keep up (its
+    # queue grows for the whole trace), so this run measures its capacity
+    k1 = min(n_requests, 20_000)
+    out["one_at_a_time_overloaded"] = run("one_at_a_time (overloaded)", one, t, k1)
+    out["one_at_a_time_overloaded"]["note"] = "offered the same load; capacity = GBps; latency unbounded"
+    # sequential baseline at a load it sustains: half of that capacity, the
+    # same trace shape, served one at a time and continuously
+    cap = out["one_at_a_time_overloaded"]["GBps"]
+    rate_lo = 0.5 * cap * 1e9 / mean_len
+    t_lo = synth.serve_trace(10_000, seed=6, n_columns=16, column_bytes=col_bytes, rate_per_s=rate_lo,
+                             lo=64, hi=64 * MiB)
+    out["at_half_sequential_capacity"] = {
+        "offered_GBps": round(0.5 * cap, 1), "offered_req_per_s": round(rate_lo),
+        "one_at_a_time": run("one_at_a_time at half its capacity", one, t_lo, 10_000),
+        "continuous": run("continuous at half the sequential capacity", None, t_lo, 10_000)}
     # the same server near saturation: 0.9 of the plain bandwidth, 50,000 requests
     rate_hi = 0.9 * plain_gbps * 1e9 / mean_len
     t_hi = synth.serve_trace(50_000, seed=5, n_columns=16, column_bytes=col_bytes, rate_per_s=rate_hi,
@@ -340,6 +390,11 @@ def main():
     ap.add_argument("--ablation", action="store_true",
                     help="time the three accumulation schedules (ppc_pospopcnt_variant 0/1/2) on "
                          "256 MiB at w = 16 and exit (short: also the command to profile them)")
+    ap.add_argument("--profile-batched", action="store_true",
+                    help="run for rocprofv3 counters on the batched form: the 10,000-array pool filled by "
+                         "a few large generator kernels, one plan with the tuned setting (256 tiles per "
+                         "item, 1024 waves; no autotuning), 3 runs, then 3 plain 256 MiB device copies "
+                         "(counter calibration)")
     ap.add_argument("--profile", action="store_true",
                     help="run for rocprofv3: the plain loop (warm-up + steps), the read roofline as "
                          "often, and 3 plain 256 MiB device copies (counter calibration)")
@@ -360,6 +415,27 @@ def main():
     log("device: %s" % torch.cuda.get_device_name(dev))
     if args.sweep:
         size_sweep(ppc, torch, synth, dev, args.sweep_out)
+        return
+    if args.profile_batched:
+        spec = synth.batch_spec(10_000, seed=3)
+        n = len(spec["lengths"])
+        pool = torch.empty(spec["pool_bytes"] + 128, dtype=torch.uint8, device=dev)
+        synth.device_bernoulli(spec["pool_bytes"] + 128, 0.5, seed=3, device=dev, out=pool)
+        counts_b = torch.zeros((n, 64), dtype=torch.int64, device=dev)
+        base, cbase = pool.data_ptr(), counts_b.data_ptr()
+        descs = ppc.make_descs([base + int(o) for o in spec["offsets"]], spec["lengths"],
+                               [cbase + i * 512 for i in range(n)], spec["widths"])
+        plan = ppc.ppc_plan_create(descs, n, ppc.ppc_plan_opts(256, 1024, 0, 1, 0))
+        try:
+            for _ in range(3):
+                ppc.ppc_plan_run(plan)
+            dst = torch.empty(CALL_BYTES, dtype=torch.uint8, device=dev)
+            for i in range(3):
+                dst.copy_(pool[i * CALL_BYTES:(i + 1) * CALL_BYTES])
+            torch.cuda.synchronize()
+        finally:
+            ppc.ppc_plan_destroy(plan)
+        log("profile-batched run done: %d arrays, %d bytes per plan run" % (n, int(spec["lengths"].sum())))
         return
     if args.ablation:
         abufs = [synth.device_bernoulli(CALL_BYTES, 0.5, seed=30 + i, device=dev) for i in range(4)]
@@ -422,11 +498,40 @@ def main():
     total_bytes = args.steps * len(WIDTHS) * CALL_BYTES
     value = total_bytes / wall / 1e9
 
-    # kernel timing: the same rotation again, every launch carrying a HIP event
-    # pair that its own dispatch records (kernel start and end on the launch
-    # stream), for at least K steps and `--kernel-seconds` of accumulated
-    # kernel time.  Such events leave the queue idle for ~5 us after each
-    # kernel, which is why the whole-job pass above runs without them.
+    # back-to-back kernel timing (the roofline figure): the same rotation of
+    # K steps again, one HIP event pair on the launch stream around each
+    # pass, repeated for at least `--kernel-seconds` of GPU time.  The
+    # per-launch interval is what a kernel costs when launches follow each
+    # other on one stream.
+    stream = torch.cuda.current_stream()
+    lib, sp = ppc.lib(), stream.cuda_stream
+    cptr = {w: counts[w].data_ptr() for w in WIDTHS}
+    bptr = [b.data_ptr() for b in bufs]
+    b2b_ms, b2b_launches = 0.0, 0
+    b2b_w = {w: [] for w in WIDTHS}
+    while b2b_launches < args.steps * len(WIDTHS) or b2b_ms < args.kernel_seconds * 1e3:
+        for j, w in enumerate(WIDTHS):  # one width at a time: per-width intervals
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(args.steps):
+                lib.ppc_pospopcnt(w, cptr[w], bptr[(i + j) % 4], CALL_BYTES, sp)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            b2b_w[w].append(ms / args.steps)
+            b2b_ms += ms
+            b2b_launches += args.steps
+    b2b_avg_ms = b2b_ms / b2b_launches
+    achieved = CALL_BYTES / (b2b_avg_ms * 1e-3) / 1e9
+    per_width_b2b = {str(w): round(CALL_BYTES / (sum(v) / len(v) * 1e-3) / 1e9, 1) for w, v in b2b_w.items()}
+    log("plain: %.1f GB/s whole-job (%.2f us per call); back to back %.2f us per launch over %d launches "
+        "-> %.1f GB/s" % (value, wall / (args.steps * len(WIDTHS)) * 1e6, b2b_avg_ms * 1e3, b2b_launches,
+                          achieved))
+
+    # idle-queue kernel timing: every launch carries a HIP event pair that its
+    # own dispatch records (kernel start and end), for at least K steps and
+    # `--kernel-seconds` of kernel time.  Such events leave the queue idle for
+    # ~5 us after each kernel, so every launch starts on an idle queue.
     ev = [(ppc.HipEvent(), ppc.HipEvent()) for _ in range(args.steps * len(WIDTHS))]
     per_call = {w: [] for w in WIDTHS}
     kernel_s, steps_timed = 0.0, 0
@@ -448,9 +553,9 @@ def main():
     wall_timed = time.perf_counter() - t1
     all_ms = sorted(x for v in per_call.values() for x in v)
     avg_ms = sum(all_ms) / len(all_ms)
-    achieved = CALL_BYTES / (avg_ms * 1e-3) / 1e9
-    log("plain: %.1f GB/s whole-job (%.2f us per call), kernel avg %.2f us over %d launches -> %.1f GB/s"
-        % (value, wall / (args.steps * len(WIDTHS)) * 1e6, avg_ms * 1e3, len(all_ms), achieved))
+    achieved_idle = CALL_BYTES / (avg_ms * 1e-3) / 1e9
+    log("plain, idle-queue launches: kernel avg %.2f us over %d launches -> %.1f GB/s"
+        % (avg_ms * 1e3, len(all_ms), achieved_idle))
 
     # read-only roofline kernel on the same buffers
     sink = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -459,18 +564,44 @@ def main():
     rl = dispatch_timed(lambda b, e0, e1: ppc.ppc_read_roofline_timed(sink, b, start_event=e0, stop_event=e1),
                         bufs, 4 * args.steps, torch)
     rl_gbps = CALL_BYTES / (sum(rl) / len(rl) * 1e-3) / 1e9
-    log("read roofline: %.1f GB/s" % rl_gbps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(4 * args.steps):
+        lib.ppc_read_roofline(sink.data_ptr(), bptr[i % 4], CALL_BYTES, sp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    rl_b2b_gbps = CALL_BYTES * 4 * args.steps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    log("read roofline: %.1f GB/s idle-queue, %.1f GB/s back to back" % (rl_gbps, rl_b2b_gbps))
 
-    # density does not change the speed (all-integer, data-independent work)
+    # density does not change the speed (all-integer, data-independent work):
+    # every width at p = 0.01, 0.5, 0.99, back to back over 4 rotating
+    # buffers of that density, each for at least `--kernel-seconds`
+    def b2b_gbps(cbufs, w):
+        done_ms, n = 0.0, 0
+        cp = counts[w].data_ptr()
+        ptrs = [b.data_ptr() for b in cbufs]
+        while done_ms < args.kernel_seconds * 1e3 or n < 100:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for i in range(100):
+                lib.ppc_pospopcnt(w, cp, ptrs[i % len(ptrs)], CALL_BYTES, sp)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            done_ms += e0.elapsed_time(e1)
+            n += 100
+        return {"GBps": round(CALL_BYTES * n / (done_ms * 1e-3) / 1e9, 1),
+                "us_per_launch": round(done_ms / n * 1e3, 2), "launches": n}
+
     density = {}
-    for p in (0.01, 0.99):
-        dbufs = [synth.device_bernoulli(CALL_BYTES, p, seed=20 + i, device=dev) for i in range(4)]
-        c16 = torch.zeros(16, dtype=torch.int64, device=dev)
-        ms = dispatch_timed(lambda b, e0, e1: ppc.ppc_pospopcnt_timed(16, c16, b, start_event=e0, stop_event=e1),
-                            dbufs, 4 * args.steps, torch)
-        density[str(p)] = round(CALL_BYTES / (sum(ms) / len(ms) * 1e-3) / 1e9, 1)
-        del dbufs
-    density["0.5"] = round(CALL_BYTES / (sum(per_call[16]) / len(per_call[16]) * 1e-3) / 1e9, 1)
+    for p in (0.01, 0.5, 0.99):
+        dbufs = bufs if p == 0.5 else [synth.device_bernoulli(CALL_BYTES, p, seed=20 + i, device=dev)
+                                       for i in range(4)]
+        torch.cuda.synchronize()
+        density[str(p)] = {str(w): b2b_gbps(dbufs, w) for w in WIDTHS}
+        if p != 0.5:
+            del dbufs
+    log("density matrix (GB/s back to back): " + "; ".join(
+        "p=%s: %s" % (p, " ".join("%s" % v[str(w)]["GBps"] for w in WIDTHS)) for p, v in density.items()))
 
     def us_stats(v):
         v = sorted(v)
@@ -497,7 +628,7 @@ def main():
     small_ms = sorted(dispatch_timed(lambda b, e0, e1: ppc.ppc_pospopcnt_timed(16, c16, b, start_event=e0,
                                                                                  stop_event=e1),
                                      [small], 200, torch))
-    lib, st = ppc.lib(), torch.cuda.current_stream().cuda_stream
+    st = sp
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(500):
@@ -523,19 +654,29 @@ def main():
                    "bytes_per_call": CALL_BYTES, "calls_per_step": len(WIDTHS)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic_from_profiles()},
+                     "traffic": traffic_from_profiles(),
+                     "achieved_idle_queue": round(achieved_idle, 1),
+                     "frac_idle_queue": round(achieved_idle / HBM_PEAK_GBPS, 4),
+                     "measure": "achieved/frac: launches back to back on one stream, a HIP event pair on that "
+                                "stream around each pass of K launches (%d launches, %.2f us per launch); "
+                                "achieved_idle_queue/frac_idle_queue: events recorded by each launch's own "
+                                "dispatch, every launch starting on an idle queue (%d launches, %.2f us avg)"
+                                % (b2b_launches, b2b_avg_ms * 1e3, len(all_ms), avg_ms * 1e3)},
         "kernel_avg_us": round(avg_ms * 1e3, 2),
         "kernel_us": us_stats(all_ms) | {"seconds": round(kernel_s, 3)},
         "kernel_us_per_width": per_width_us,
+        "b2b_us_per_launch": round(b2b_avg_ms * 1e3, 2),
         "wall_us_per_call": round(wall / (args.steps * len(WIDTHS)) * 1e6, 2),
-        "timing": "value: K steps of plain calls, host clock between synchronisations; "
-                  "roofline.achieved: the same rotation again with dispatch-recorded HIP events "
-                  "on every launch, for at least K steps and %.1f s of kernel time (%d launches; whole-job "
-                  "rate of that pass, which synchronises every K steps: %.1f GB/s)"
-                  % (args.kernel_seconds, len(all_ms), steps_timed * len(WIDTHS) * CALL_BYTES / wall_timed / 1e9),
+        "timing": "value: K steps of plain calls (4 widths each), host clock between two synchronisations; "
+                  "roofline.achieved: the same calls back to back, GPU events around each pass, at least "
+                  "%.1f s; per_width_GBps and kernel_us_per_width: idle-queue launches (whole-job rate of "
+                  "that pass, which leaves the queue idle after every kernel: %.1f GB/s)"
+                  % (args.kernel_seconds, steps_timed * len(WIDTHS) * CALL_BYTES / wall_timed / 1e9),
         "per_width_GBps": per_width,
-        "density_GBps_w16": density,
+        "per_width_b2b_GBps": per_width_b2b,
+        "density_GBps_b2b": density,
         "read_roofline_GBps": round(rl_gbps, 1),
+        "read_roofline_b2b_GBps": round(rl_b2b_gbps, 1),
         "shard_32MiB_w16": {"kernel_avg_us": round(shard_us, 2),
                             "GBps": round(32 * MiB / (shard_us * 1e-6) / 1e9, 1),
                             "frac": round(32 * MiB / (shard_us * 1e-6) / 1e9 / HBM_PEAK_GBPS, 4),
@@ -545,7 +686,8 @@ def main():
                              "kernel_GBps": round(2 * MiB / (small_ms[len(small_ms) // 2] * 1e-3) / 1e9, 1),
                              "wall_us_per_call": round(small_wall_us, 2),
                              "note": "latency-bound: one kernel launch per 2 MiB"},
-        "frac_of_read_roofline": round(achieved / rl_gbps, 4),
+        "frac_of_read_roofline": round(achieved / rl_b2b_gbps, 4),
+        "frac_of_read_roofline_idle_queue": round(achieved_idle / rl_gbps, 4),
     }
     del bufs
     torch.cuda.empty_cache()
