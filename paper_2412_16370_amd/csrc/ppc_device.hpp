@@ -110,14 +110,13 @@ struct Planes {
 __device__ __forceinline__ uint32_t bit_length(uint32_t k) { return 32u - (uint32_t)__builtin_clz(k | 1u) - (k == 0u ? 1u : 0u); }
 
 // ---- cross-lane helpers --------------------------------------------------
-// ds_swizzle in bit mode: lane j reads lane (j ^ x) inside its 32-lane half.
-template <int X>
-__device__ __forceinline__ uint32_t swz_xor(uint32_t v) {
-    static_assert(X > 0 && X < 32, "xor mask inside a 32-lane group");
-    return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x1f | (X << 10));
-}
-
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// v_permlane16_swap of a value with itself: element 0 keeps rows 0 and 2
+// (lanes 0-15, 32-47) and holds the partner's value (lane ^ 16) in rows 1
+// and 3; element 1 holds the partner's value in rows 0 and 2 and keeps rows
+// 1 and 3.  One VALU instruction, no LDS traffic.
+__device__ __forceinline__ auto swap16(uint32_t x) { return __builtin_amdgcn_permlane16_swap(x, x, false, false); }
 
 // Index of the calling wave inside its block, as a wave-uniform (scalar)
 // value, so that loops and branches derived from it stay scalar.
@@ -125,10 +124,10 @@ __device__ __forceinline__ uint32_t wave_in_block() {
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
 }
 
-// Partner value for lane ^ S inside a 32-lane half.  DPP row operations
-// where gfx950 has one (xor 1 and 2 by quad permutation, xor 8 by a row
-// rotation by 8, xor 4 by a left and a right row shift merged per bank);
-// the LDS-pipe swizzle for xor 16.
+// Partner value for lane ^ S inside a 32-lane half, without the LDS: DPP
+// row operations for xor 1 and 2 (quad permutation), xor 4 (a left and a
+// right row shift merged per bank) and xor 8 (row rotation by 8);
+// v_permlane16_swap for xor 16.
 template <int S>
 __device__ __forceinline__ uint32_t partner_xor(uint32_t x) {
     if constexpr (S == 1) {
@@ -143,7 +142,9 @@ __device__ __forceinline__ uint32_t partner_xor(uint32_t x) {
     } else if constexpr (S == 8) {
         return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x128, 0xF, 0xF, true);  // row_ror:8
     } else {
-        return swz_xor<S>(x);
+        static_assert(S == 16, "xor 1, 2, 4, 8 or 16");
+        const auto sw = swap16(x);
+        return (lane_id() & 16u) ? sw[0] : sw[1];
     }
 }
 
@@ -156,13 +157,17 @@ __device__ __forceinline__ uint32_t partner_xor(uint32_t x) {
 // merges the partner's bytes; stages 4, 2 and 1 rotate the partner's word
 // and merge it by a bit mask.
 struct TransposeConsts {
-    uint32_t sel16, sel8;  // v_perm_b32 selectors: bytes 0-3 = own word, 4-7 = partner's
+    // v_perm_b32 selectors.  Stage 8: bytes 0-3 = own word, 4-7 = partner's.
+    // Stage 16 permutes the pair (e1, e0) of swap16, whose own/partner order
+    // depends on the row: bytes 0-3 = e0, 4-7 = e1.
+    uint32_t sel16, sel8;
     uint32_t take[3], rot[3];  // stages 4, 2, 1
     __device__ __forceinline__ TransposeConsts() {
         const uint32_t lane = lane_id();
-        // row bit 4 clear: keep own bytes 0,1, take partner's bytes 0,1 as 2,3;
-        // set: take partner's bytes 2,3 as 0,1, keep own bytes 2,3
-        sel16 = (lane & 16u) ? 0x03020706u : 0x05040100u;
+        // row bit 4 clear (e0 = own, e1 = partner): keep own bytes 0,1, take
+        // the partner's bytes 0,1 as 2,3; set (e0 = partner, e1 = own): take
+        // the partner's bytes 2,3 as 0,1, keep own bytes 2,3
+        sel16 = (lane & 16u) ? 0x07060302u : 0x05040100u;
         // row bit 3 clear: own bytes 0,2 stay, partner's bytes 0,2 go to 1,3;
         // set: partner's bytes 1,3 go to 0,2, own bytes 1,3 stay
         sel8 = (lane & 8u) ? 0x03070105u : 0x06020400u;
@@ -185,23 +190,26 @@ __device__ __forceinline__ uint32_t merge_rotated(uint32_t own, uint32_t partner
 }
 
 // Transposes NZ planes stage by stage (every plane's partner fetches of a
-// stage are issued before any of them is consumed, so the LDS swizzles of
-// the xor-16 and xor-4 stages overlap and DPP reads never wait on the
-// previous instruction), then returns in lane r (inside each half) the sum
-// over planes of popcount(column r of plane e) << e.
+// stage are issued before any of them is consumed, so a DPP read never
+// waits on the instruction before it), then returns in lane r (inside each
+// half) the sum over planes of popcount(column r of plane e) << e.  Every
+// partner fetch is a VALU instruction (v_permlane16_swap, DPP): measured
+// 0.05-0.15 us faster per 256 MiB launch than LDS-pipe swizzles for the
+// xor-16 and xor-4 stages.
 template <int NZ>
 __device__ __forceinline__ uint32_t transpose_popcount(uint32_t (&z)[NZ], const TransposeConsts &tc) {
     uint32_t t[NZ];
 #pragma unroll
-    for (int e = 0; e < NZ; ++e) t[e] = swz_xor<16>(z[e]);
-#pragma unroll
-    for (int e = 0; e < NZ; ++e) z[e] = __builtin_amdgcn_perm(t[e], z[e], tc.sel16);
+    for (int e = 0; e < NZ; ++e) {
+        const auto sw = swap16(z[e]);
+        z[e] = __builtin_amdgcn_perm(sw[1], sw[0], tc.sel16);
+    }
 #pragma unroll
     for (int e = 0; e < NZ; ++e) t[e] = partner_xor<8>(z[e]);
 #pragma unroll
     for (int e = 0; e < NZ; ++e) z[e] = __builtin_amdgcn_perm(t[e], z[e], tc.sel8);
 #pragma unroll
-    for (int e = 0; e < NZ; ++e) t[e] = swz_xor<4>(z[e]);
+    for (int e = 0; e < NZ; ++e) t[e] = partner_xor<4>(z[e]);
 #pragma unroll
     for (int e = 0; e < NZ; ++e) z[e] = merge_rotated(z[e], t[e], tc.take[0], tc.rot[0]);
 #pragma unroll
