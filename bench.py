@@ -196,6 +196,14 @@ def batched_leg(ppc, torch, synth, dev, reps):
     ms = time_calls(lambda b, i: ppc.ppc_plan_run(plan), [None], reps, torch)
     ppc.ppc_plan_destroy(plan)
     batched_ms = sorted(ms)[len(ms) // 2]
+    # the allocation-free batched call on the same arrays: descriptors in
+    # device memory, tables built on the device every call
+    raw = ppc.descs_bytes(ppc.make_descs(addrs, spec["lengths"], caddr, spec["widths"]))
+    descs_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+    torch.cuda.synchronize()
+    na_ms = sorted(time_calls(lambda b, i: ppc.ppc_batch_noalloc(descs_dev, n), [None], reps, torch))
+    noalloc_ms = na_ms[len(na_ms) // 2]
+    del descs_dev
     # the same arrays as 10,000 plain calls back to back on one stream
     lib = ppc.lib()
     widths = [int(w) for w in spec["widths"]]
@@ -219,6 +227,7 @@ def batched_leg(ppc, torch, synth, dev, reps):
             "plain_calls_GBps": round(total / (plain_med * 1e-3) / 1e9, 1),
             "plain_calls_ms": round(plain_med, 3),
             "speedup_vs_plain": round(plain_med / batched_ms, 3),
+            "noalloc_GBps": round(total / (noalloc_ms * 1e-3) / 1e9, 1), "noalloc_ms": round(noalloc_ms, 3),
             "tiles_per_item": info["tiles_per_item"], "waves": info["waves"],
             "n_items": info["n_items"], "tuned": ["given", "measured", "cache"][info["tuned"]],
             "plan_create_s": round(create_s, 3)}

@@ -146,3 +146,22 @@ def test_invalid_descriptor_counts_nothing_and_next_call_is_clean(ppc):
     check_against_oracle(got, pool, spec)
     with pytest.raises(ppc.PpcError):
         ppc.ppc_batch_noalloc(to_device(ppc, descs), 65537, None)
+
+
+def test_maximum_array_count(ppc):
+    """PPC_NOALLOC_MAX_ARRAYS arrays in one call (short, unaligned, every
+    width, a few of several MiB among them): every array equals the oracle."""
+    n = 65536
+    rng = np.random.default_rng(45)
+    lengths = rng.integers(0, 300, size=n)
+    lengths[rng.choice(n, size=8, replace=False)] = rng.integers(1 << 20, 6 << 20, size=8)
+    widths = rng.choice(np.array([8, 16, 32, 64]), size=n)
+    offsets = np.empty(n, dtype=np.int64)
+    pos = 0
+    for i in range(n):
+        offsets[i] = pos + int(rng.integers(0, 16))
+        pos = int(offsets[i] + lengths[i])
+    spec = dict(offsets=offsets, lengths=lengths, widths=widths, p=np.full(n, 0.5), pool_bytes=pos + 64)
+    pool = synth.device_bernoulli(pos + 64, 0.5, seed=45, device=dev())
+    got = noalloc_counts(ppc, pool, spec)
+    check_against_oracle(got, pool, spec)
