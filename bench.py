@@ -380,6 +380,76 @@ def size_sweep(ppc, torch, synth, dev, out_path):
             log("sweep %11d B: w16 %9.2f us %9.1f GB/s" % (n, row["w16_us"], row["w16_GBps"]))
 
 
+def batched_size_sweep(ppc, torch, synth, dev, out_path):
+    """The batched forms by array length: for each length L (2^i and 3*2^i
+    bytes, 16 B to 16 MiB), N equal arrays of L bytes (N = 1 GiB / L, at
+    least 64 and at most 65,536; widths cycling through 8, 16, 32, 64;
+    starts 256 bytes apart or more).  Timed: one plan over the N arrays
+    (default options: autotuned, graph replay), the allocation-free call over the same
+    descriptors, each repeated for at least 10 runs and 20 ms (median), and
+    256 plain calls on the first 256 arrays back to back through the raw C
+    entry point (mean per call).  GB/s = bytes counted / time."""
+    sizes = sorted([1 << i for i in range(4, 25)] + [3 << i for i in range(3, 23)])
+    pool = synth.device_bernoulli(1 << 30, 0.5, seed=61, device=dev)
+    counts = torch.zeros((65536, 64), dtype=torch.int64, device=dev)
+    lib, stream = ppc.lib(), torch.cuda.current_stream()
+    base, cb = pool.data_ptr(), counts.data_ptr()
+
+    def median_ms(fn):
+        for _ in range(3):
+            fn(None, 0)
+        torch.cuda.synchronize()
+        times = []
+        while len(times) < 10 or sum(times) < 20.0:
+            times += time_calls(fn, [None], 10, torch)
+        return sorted(times)[len(times) // 2]
+
+    if os.path.dirname(out_path):
+        os.makedirs(os.path.dirname(out_path), exist_ok=True)
+    with open(out_path, "w") as out:
+        for L in sizes:
+            stride = (L + 255) // 256 * 256
+            n = int(max(64, min(65536, (1 << 30) // stride)))
+            addrs = [base + i * stride for i in range(n)]
+            caddr = [cb + i * 512 for i in range(n)]
+            widths = [WIDTHS[i % 4] for i in range(n)]
+            descs = ppc.make_descs(addrs, [L] * n, caddr, widths)
+            plan = ppc.ppc_plan_create(descs, n)
+            try:
+                info = ppc.ppc_plan_get_info(plan)
+                plan_ms = median_ms(lambda b, i: ppc.ppc_plan_run(plan))
+            finally:
+                ppc.ppc_plan_destroy(plan)
+            descs_dev = torch.frombuffer(bytearray(ppc.descs_bytes(descs)), dtype=torch.uint8).to(dev)
+            na_ms = median_ms(lambda b, i: ppc.ppc_batch_noalloc(descs_dev, n))
+            del descs_dev
+            k = min(n, 256)
+            st = stream.cuda_stream
+            for i in range(k):
+                lib.ppc_pospopcnt(widths[i], caddr[i], addrs[i], L, st)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record(stream)
+            for i in range(k):
+                lib.ppc_pospopcnt(widths[i], caddr[i], addrs[i], L, st)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            plain_ms = ev0.elapsed_time(ev1) / k
+            total = n * L
+            row = {"array_bytes": L, "arrays": n, "total_bytes": total,
+                   "plan_us": round(plan_ms * 1e3, 2), "plan_GBps": round(total / (plan_ms * 1e-3) / 1e9, 1),
+                   "noalloc_us": round(na_ms * 1e3, 2), "noalloc_GBps": round(total / (na_ms * 1e-3) / 1e9, 1),
+                   "plain_call_us": round(plain_ms * 1e3, 3),
+                   "plain_calls_GBps": round(L / (plain_ms * 1e-3) / 1e9, 2),
+                   "items": info["n_items"], "tiles_per_item": info["tiles_per_item"], "waves": info["waves"],
+                   "tuned": ["given", "measured", "cache"][info["tuned"]]}
+            out.write(json.dumps(row) + "\n")
+            out.flush()
+            log("batched sweep %8d B x %5d: plan %7.1f GB/s, no-alloc %7.1f GB/s, plain calls %8.2f GB/s"
+                % (L, n, row["plan_GBps"], row["noalloc_GBps"], row["plain_calls_GBps"]))
+    del pool, counts
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -394,6 +464,10 @@ def main():
                     help="length sweep of Section 5.2 (2^i and 3*2^i bytes up to 1.5 GiB) at every "
                          "width, repeated calls on one buffer as in the paper's harness; writes "
                          "JSON lines to --sweep-out and exits")
+    ap.add_argument("--sweep-batched", action="store_true",
+                    help="the batched form by array length: one plan over many equal arrays per length "
+                         "(16 B to 16 MiB, 1 GiB per plan where the array count allows); writes JSON "
+                         "lines to --sweep-out and exits")
     ap.add_argument("--sweep-out", default="size_sweep.jsonl",
                     help="JSON-lines file for --sweep (one line per size)")
     ap.add_argument("--ablation", action="store_true",
@@ -424,6 +498,9 @@ def main():
     log("device: %s" % torch.cuda.get_device_name(dev))
     if args.sweep:
         size_sweep(ppc, torch, synth, dev, args.sweep_out)
+        return
+    if args.sweep_batched:
+        batched_size_sweep(ppc, torch, synth, dev, args.sweep_out)
         return
     if args.profile_batched:
         spec = synth.batch_spec(10_000, seed=3)

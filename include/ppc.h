@@ -209,15 +209,16 @@ ppc_status ppc_plan_destroy(ppc_plan *plan);
  * optional) is given the kernels write there the number of invalid
  * descriptors (0 when the batch was counted).
  *
- * Memory.  Every table the kernels use (array table, work items, work
- * cursor) lives in one static device array of PPC_NOALLOC_SCRATCH_BYTES
- * (8 MiB) per GPU, held until the process ends; the call enqueues two
- * kernels and no copy, and calls no allocating routine.  Calls that
+ * Memory.  Every table the kernels use (array table, block sums, work
+ * items, work cursor) lives in one static device array of
+ * PPC_NOALLOC_SCRATCH_BYTES (about 8 MiB) per GPU, held until the process
+ * ends; the call enqueues four kernels and no copy, and calls no
+ * allocating routine.  Calls that
  * overlap on one GPU (other streams, other host threads) share that array
  * and race: order them on one stream.  PPC_EDEVICE if a launch fails.
  * ---------------------------------------------------------------------- */
 #define PPC_NOALLOC_MAX_ARRAYS 65536u
-#define PPC_NOALLOC_SCRATCH_BYTES (256u + 64u * 65536u + 16u * 262144u)
+#define PPC_NOALLOC_SCRATCH_BYTES (256u + 64u * 65536u + 64u * 256u + 16u * 262144u)
 
 ppc_status ppc_batch_noalloc(const ppc_desc *descs, uint32_t n, uint32_t *n_invalid, void *stream);
 

@@ -7,13 +7,15 @@
 // counters), but the descriptor table is the caller's, in device memory, and
 // every table the kernels need lives in one file-scope device array,
 // `scratch`, of fixed size:
-//   [0, 256)                      header: work cursor and item counts
+//   [0, 256)                      header: work cursor, item counts, item size
 //   [256, 256 + 64 * 2^16)        one ArrayInfo per array (at most 2^16)
+//   [.., + 64 * 256)              per-block partial sums of the setup kernels
 //   [.., + 16 * 2^18)             work items (at most 2^18), largest first
-// Two launches per call: a one-block setup kernel validates the
-// descriptors, builds the array table, picks the tiles per item and writes
-// the items; the persistent kernel then walks them.  Nothing is allocated
-// and nothing is copied from the host, so the call can be captured.
+// Four launches per call: three setup kernels over the descriptors, one
+// thread per array (array table and block sums; item size and item counts;
+// item offsets and the items themselves), then the persistent kernel that
+// walks the items.  Nothing is allocated and nothing is copied from the
+// host, so the call can be captured.
 //
 // Each GPU holds one copy of `scratch` for as long as the process runs;
 // calls that overlap on one GPU (different streams, or several host
@@ -33,21 +35,39 @@ namespace ppc {
 
 constexpr uint32_t kNaMaxArrays = PPC_NOALLOC_MAX_ARRAYS;
 constexpr uint32_t kNaMaxItems = 1u << 18;
-// Tiles per whole item: 256 tiles = 4 MiB, the setting the plan's autotuner
-// picks for mixed batches.  Raised only when the total would need more than
-// kNaMaxItems items, which takes more than 768 GiB of input in one call.
-constexpr uint32_t kNaItemTiles = 256;
+// Tiles per whole item P: about kNaItemsPerWave items per wave of the walk
+// (total tiles / (kNaItemsPerWave * waves)), kept within
+// [kNaMinItemTiles, kNaMaxItemTilesBal].  Each item ends in a drain of the
+// wave's loads, a plane reduction and w atomics, so few large items per wave
+// run fastest as long as every wave has one; 256 tiles (4 MiB) is the
+// plan's tuned size for large mixed batches.  P is raised above that only
+// when the table would need more than kNaMaxItems items, which takes more
+// than 768 GiB of input in one call.
+constexpr uint32_t kNaItemsPerWave = 1;
+constexpr uint32_t kNaMinItemTiles = 4;
+constexpr uint32_t kNaMaxItemTilesBal = 256;
 // Shorter items (one per array at most: its tiles past the last whole item,
 // or only its head/tail bytes) go into buckets by the bit length of their
 // tile count, clamped to kNaBuckets - 1, and are laid out largest bucket
 // first: the largest-first order of the plan, without a sort.  Items of at
-// most kNaGroupTiles tiles (buckets below kNaFirstSingle) are handed out
-// kNaGroup per ticket; the rest one per ticket.
+// most 3 tiles (buckets below kNaFirstSingle) are handed out kNaGroup per
+// ticket; the rest one per ticket.
 constexpr int kNaBuckets = 10;
 constexpr int kNaFirstSingle = 3;  // bit length 3: 4 tiles or more
 constexpr uint32_t kNaGroup = 16;
-constexpr int kNaSetupThreads = 1024;
+constexpr int kNaSetupThreads = 256;
+constexpr uint32_t kNaMaxBlocks = kNaMaxArrays / kNaSetupThreads;
+static_assert(kNaMaxBlocks <= (uint32_t)kNaSetupThreads, "one thread per setup block in the block scans");
 constexpr int kNaWpb = 4;
+// The walk launches kNaWavesPerCuSmall waves per CU.  All of them walk when
+// the arrays are short (fewer than kNaShortMeanTiles tiles per array on
+// average), where each item is a chain of dependent memory accesses and
+// more waves hide more of that latency; otherwise only the first
+// kNaWavesPerCu per CU do and the rest exit at once, so each SIMD streams
+// with one wave, which is faster for long items.
+constexpr uint32_t kNaWavesPerCu = 4;
+constexpr uint32_t kNaWavesPerCuSmall = 8;
+constexpr uint64_t kNaShortMeanTiles = 4;
 
 struct NaHeader {
     uint32_t cursor;     // tickets handed out after each wave's first
@@ -55,12 +75,26 @@ struct NaHeader {
     uint32_t n_items;    // all items; those past n_single go kNaGroup per ticket
     uint32_t n_tickets;  // n_single + ceil((n_items - n_single) / kNaGroup)
     uint32_t tiles_per_item;
-    uint32_t reserved[59];
+    uint32_t ok;         // 1: every descriptor valid and the items fit the table
+    uint32_t n_bad;      // invalid descriptors
+    uint32_t waves;      // waves of the walk that take tickets
+    uint32_t reserved[56];
 };
 static_assert(sizeof(NaHeader) == 256, "header size");
 
+// Sums of one setup block: its invalid descriptors and tiles (first setup
+// kernel), its item counts per bucket and its whole items (second).
+struct NaPartial {
+    uint64_t tiles;
+    uint32_t bad;
+    uint32_t cnt[kNaBuckets + 1];  // [0, kNaBuckets): buckets, [kNaBuckets]: whole items
+    uint32_t pad[2];
+};
+static_assert(sizeof(NaPartial) == 64, "partial size");
+
 constexpr size_t kNaArraysOff = sizeof(NaHeader);
-constexpr size_t kNaItemsOff = kNaArraysOff + (size_t)kNaMaxArrays * sizeof(ArrayInfo);
+constexpr size_t kNaPartOff = kNaArraysOff + (size_t)kNaMaxArrays * sizeof(ArrayInfo);
+constexpr size_t kNaItemsOff = kNaPartOff + (size_t)kNaMaxBlocks * sizeof(NaPartial);
 constexpr size_t kNaScratchBytes = kNaItemsOff + (size_t)kNaMaxItems * sizeof(WorkItem);
 static_assert(kNaScratchBytes == PPC_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
 
@@ -95,63 +129,115 @@ __device__ __forceinline__ void block_exclusive_scan(T (&v)[K], T (*lds)[kNaSetu
 // Bucket of a shorter item of t tiles (t < tiles per item).
 __device__ __forceinline__ int na_bucket(uint32_t t) { return (int)min(bit_length(t), (uint32_t)(kNaBuckets - 1)); }
 
-// One block.  Thread t handles arrays [t*per, (t+1)*per).  If any
-// descriptor is invalid, no item is written and the batch counts nothing.
-__global__ __launch_bounds__(kNaSetupThreads) void noalloc_setup_kernel(const ppc_desc *__restrict__ descs,
-                                                                        uint32_t n, uint32_t *n_invalid_out,
-                                                                        uint8_t *scr) {
-    NaHeader *h = reinterpret_cast<NaHeader *>(scr);
+// Items of one array for tiles per item P: cnt[kNaBuckets] whole items,
+// and one in the bucket of the rest (or of its head/tail bytes alone).
+__device__ __forceinline__ void na_count_items(const ArrayInfo &ai, uint32_t P, uint32_t (&cnt)[kNaBuckets + 1]) {
+    const bool edges = ai.edge0_len + ai.edge1_len > 0u;
+    const uint32_t rest = ai.n_tiles % P;
+    cnt[kNaBuckets] += ai.n_tiles / P;
+    if (rest != 0u || (ai.n_tiles == 0u && edges)) ++cnt[na_bucket(rest)];
+}
+
+// Setup 1, thread i <-> array i: validates the descriptor, writes the array
+// table entry, and the block's sums of invalid descriptors and tiles.
+__global__ __launch_bounds__(kNaSetupThreads) void noalloc_arrays_kernel(const ppc_desc *__restrict__ descs,
+                                                                         uint32_t n, uint8_t *scr) {
     ArrayInfo *arrays = reinterpret_cast<ArrayInfo *>(scr + kNaArraysOff);
-    WorkItem *items = reinterpret_cast<WorkItem *>(scr + kNaItemsOff);
+    NaPartial *part = reinterpret_cast<NaPartial *>(scr + kNaPartOff);
     __shared__ uint64_t lds64[1][kNaSetupThreads];
-    __shared__ uint32_t lds32[kNaBuckets + 2][kNaSetupThreads];
-
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (n + kNaSetupThreads - 1) / kNaSetupThreads;
-    const uint32_t a0 = min(n, tid * per), a1 = min(n, a0 + per);
-
-    // pass 1: the array table, invalid descriptors, total tiles
+    __shared__ uint32_t lds32[1][kNaSetupThreads];
+    const uint32_t i = blockIdx.x * kNaSetupThreads + threadIdx.x;
     uint32_t bad[1] = {0};
     uint64_t tiles[1] = {0};
-    for (uint32_t i = a0; i < a1; ++i) {
+    if (i < n) {
         const ppc_desc d = descs[i];
         ArrayInfo ai;
         if (d.reserved != 0u || !make_array_info(ai, d.buf, d.nbytes, d.counts, d.width)) {
-            ++bad[0];
+            bad[0] = 1u;
             ai = ArrayInfo{};
         }
         arrays[i] = ai;
-        tiles[0] += ai.n_tiles;
+        tiles[0] = ai.n_tiles;
     }
+    uint32_t sb[1];
+    uint64_t st[1];
+    block_exclusive_scan<uint32_t, 1>(bad, lds32, sb);
+    block_exclusive_scan<uint64_t, 1>(tiles, lds64, st);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x].bad = sb[0];
+        part[blockIdx.x].tiles = st[0];
+    }
+}
+
+// Setup 2: every block sums the first kernel's block sums (the same totals
+// in every block), picks the walking waves (of `cus` CUs) and the tiles per
+// whole item, and writes its own item counts per bucket; block 0 records the
+// choices in the header.
+__global__ __launch_bounds__(kNaSetupThreads) void noalloc_count_kernel(uint32_t n, uint32_t cus, uint8_t *scr) {
+    NaHeader *h = reinterpret_cast<NaHeader *>(scr);
+    const ArrayInfo *arrays = reinterpret_cast<const ArrayInfo *>(scr + kNaArraysOff);
+    NaPartial *part = reinterpret_cast<NaPartial *>(scr + kNaPartOff);
+    __shared__ uint64_t lds64[1][kNaSetupThreads];
+    __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupThreads];
+    const uint32_t tid = threadIdx.x, nb = gridDim.x;
+    uint32_t bad[1] = {tid < nb ? part[tid].bad : 0u};
+    uint64_t tiles[1] = {tid < nb ? part[tid].tiles : 0ull};
     uint32_t n_bad[1];
     uint64_t n_tiles[1];
     block_exclusive_scan<uint32_t, 1>(bad, lds32, n_bad);
     block_exclusive_scan<uint64_t, 1>(tiles, lds64, n_tiles);
 
-    // tiles per whole item: every array gives at most n_tiles/P + 1 items,
-    // so P >= n_tiles / (kNaMaxItems - n) keeps the total within the table
-    const uint64_t room = (uint64_t)kNaMaxItems - n;
-    const uint64_t p64 = max((uint64_t)kNaItemTiles, (n_tiles[0] + room - 1) / room);
+    // every array gives at most n_tiles/P + 1 items, so P >= n_tiles /
+    // (kNaMaxItems - n) keeps the total within the table
+    const uint64_t T = n_tiles[0], room = (uint64_t)kNaMaxItems - n;
+    const uint32_t waves = (T < kNaShortMeanTiles * n ? kNaWavesPerCuSmall : kNaWavesPerCu) * max(cus, 1u);
+    const uint64_t per_wave = (uint64_t)kNaItemsPerWave * waves;
+    const uint64_t bal = min(max((T + per_wave - 1) / per_wave, (uint64_t)kNaMinItemTiles), (uint64_t)kNaMaxItemTilesBal);
+    const uint64_t p64 = max(bal, (T + room - 1) / room);
     const bool ok = n_bad[0] == 0u && p64 <= (uint64_t)kMaxItemTiles;
     const uint32_t P = (uint32_t)min(p64, (uint64_t)kMaxItemTiles);
 
-    // pass 2: items per thread: whole ones, and per bucket the shorter ones
-    // (one at most per array)
-    uint32_t cnt[kNaBuckets + 1] = {0};  // [0, kNaBuckets): buckets, [kNaBuckets]: whole items
-    if (ok) {
-        for (uint32_t i = a0; i < a1; ++i) {
-            const ArrayInfo &ai = arrays[i];
-            const bool edges = ai.edge0_len + ai.edge1_len > 0u;
-            const uint32_t rest = ai.n_tiles % P;
-            cnt[kNaBuckets] += ai.n_tiles / P;
-            if (rest != 0u || (ai.n_tiles == 0u && edges)) ++cnt[na_bucket(rest)];
-        }
-    }
+    const uint32_t i = blockIdx.x * kNaSetupThreads + tid;
+    uint32_t cnt[kNaBuckets + 1] = {0};
+    if (ok && i < n) na_count_items(arrays[i], P, cnt);
     uint32_t tot[kNaBuckets + 1];
     block_exclusive_scan<uint32_t, kNaBuckets + 1>(cnt, lds32, tot);
+    if (tid == 0) {
+        for (int k = 0; k <= kNaBuckets; ++k) part[blockIdx.x].cnt[k] = tot[k];
+        if (blockIdx.x == 0) {
+            h->tiles_per_item = P;
+            h->ok = ok ? 1u : 0u;
+            h->n_bad = n_bad[0];
+            h->waves = waves;
+        }
+    }
+}
 
-    // layout: whole items, then buckets from the largest down
-    uint32_t base[kNaBuckets];
+// Setup 3: every block scans the blocks' item counts (the same layout in
+// every block): whole items first, then the buckets from the largest down;
+// within each, blocks in order and arrays in order.  Then thread i writes
+// array i's items; an array's first item carries its head/tail bytes.
+// Block 0 completes the header and reports invalid descriptors.
+__global__ __launch_bounds__(kNaSetupThreads) void noalloc_items_kernel(uint32_t n, uint32_t *n_invalid_out,
+                                                                        uint8_t *scr) {
+    NaHeader *h = reinterpret_cast<NaHeader *>(scr);
+    const ArrayInfo *arrays = reinterpret_cast<const ArrayInfo *>(scr + kNaArraysOff);
+    const NaPartial *part = reinterpret_cast<const NaPartial *>(scr + kNaPartOff);
+    WorkItem *items = reinterpret_cast<WorkItem *>(scr + kNaItemsOff);
+    __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupThreads];
+    __shared__ uint32_t blk_base[kNaBuckets + 1];
+    const uint32_t tid = threadIdx.x, nb = gridDim.x;
+    const uint32_t P = h->tiles_per_item;
+    const bool ok = h->ok != 0u;
+
+    uint32_t blk[kNaBuckets + 1], tot[kNaBuckets + 1];
+#pragma unroll
+    for (int k = 0; k <= kNaBuckets; ++k) blk[k] = tid < nb ? part[tid].cnt[k] : 0u;
+    block_exclusive_scan<uint32_t, kNaBuckets + 1>(blk, lds32, tot);
+    if (tid == blockIdx.x)
+        for (int k = 0; k <= kNaBuckets; ++k) blk_base[k] = blk[k];
+    uint32_t base[kNaBuckets + 1];
+    base[kNaBuckets] = 0u;
     uint32_t next = tot[kNaBuckets];
     for (int k = kNaBuckets - 1; k >= 0; --k) {
         base[k] = next;
@@ -160,33 +246,35 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_setup_kernel(const pp
     const uint32_t n_items = next;
     const uint32_t n_single = base[kNaFirstSingle] + tot[kNaFirstSingle];
 
-    // pass 3: write the items; an array's first item carries its edges
-    if (ok) {
-        uint32_t f = cnt[kNaBuckets];
-        for (uint32_t i = a0; i < a1; ++i) {
-            const ArrayInfo &ai = arrays[i];
-            const uint32_t edges = ai.edge0_len + ai.edge1_len > 0u ? 1u : 0u;
-            const uint32_t whole = ai.n_tiles / P, rest = ai.n_tiles % P;
-            for (uint32_t k = 0; k < whole; ++k) items[f++] = WorkItem{i, k * P, (k + 1u) * P, k == 0u ? edges : 0u};
-            if (rest != 0u || (ai.n_tiles == 0u && edges)) {
-                const int b = na_bucket(rest);
-                items[base[b] + cnt[b]++] = WorkItem{i, whole * P, ai.n_tiles, whole == 0u ? edges : 0u};
-            }
+    const uint32_t i = blockIdx.x * kNaSetupThreads + tid;
+    uint32_t cnt[kNaBuckets + 1] = {0};
+    if (ok && i < n) na_count_items(arrays[i], P, cnt);
+    uint32_t unused[kNaBuckets + 1];
+    block_exclusive_scan<uint32_t, kNaBuckets + 1>(cnt, lds32, unused);  // also orders blk_base
+    if (ok && i < n) {
+        const ArrayInfo &ai = arrays[i];
+        const uint32_t edges = ai.edge0_len + ai.edge1_len > 0u ? 1u : 0u;
+        const uint32_t whole = ai.n_tiles / P, rest = ai.n_tiles % P;
+        uint32_t f = base[kNaBuckets] + blk_base[kNaBuckets] + cnt[kNaBuckets];
+        for (uint32_t k = 0; k < whole; ++k) items[f++] = WorkItem{i, k * P, (k + 1u) * P, k == 0u ? edges : 0u};
+        if (rest != 0u || (ai.n_tiles == 0u && edges)) {
+            const int b = na_bucket(rest);
+            items[base[b] + blk_base[b] + cnt[b]] = WorkItem{i, whole * P, ai.n_tiles, whole == 0u ? edges : 0u};
         }
     }
-    if (tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         h->cursor = 0u;
         h->n_single = ok ? n_single : 0u;
         h->n_items = ok ? n_items : 0u;
         h->n_tickets = ok ? n_single + (n_items - n_single + kNaGroup - 1u) / kNaGroup : 0u;
-        h->tiles_per_item = P;
-        if (n_invalid_out) *n_invalid_out = ok ? 0u : (n_bad[0] ? n_bad[0] : n);
+        if (n_invalid_out) *n_invalid_out = ok ? 0u : (h->n_bad ? h->n_bad : n);
     }
 }
 
-// Persistent walk: wave g starts with ticket g, then takes tickets from the
-// cursor once its current one is done.  Ticket t < n_single is item t;
-// later tickets are runs of kNaGroup items.
+// Persistent walk: of the launched waves, the first `waves` (from the
+// header) walk and the rest exit.  Wave g starts with ticket g, then takes
+// tickets from the cursor once its current one is done.  Ticket
+// t < n_single is item t; later tickets are runs of kNaGroup items.
 template <int WPB>
 __global__ __launch_bounds__(WPB *kWave) void noalloc_batched_kernel(uint8_t *scr) {
     NaHeader *h = reinterpret_cast<NaHeader *>(scr);
@@ -195,8 +283,9 @@ __global__ __launch_bounds__(WPB *kWave) void noalloc_batched_kernel(uint8_t *sc
     const uint32_t n_tickets = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->n_tickets);
     const uint32_t n_single = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->n_single);
     const uint32_t n_items = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->n_items);
-    const uint32_t nw = gridDim.x * WPB;
+    const uint32_t nw = min((uint32_t)__builtin_amdgcn_readfirstlane((int)h->waves), gridDim.x * WPB);
     uint32_t t = blockIdx.x * WPB + wave_in_block();
+    if (t >= nw) return;
     while (t < n_tickets) {
         if (t < n_single) {
             run_item(arrays, items[t]);
@@ -242,12 +331,15 @@ ppc_status ppc_batch_noalloc(const ppc_desc *descs, uint32_t n, uint32_t *n_inva
     uint8_t *scr = noalloc_scratch(dev);
     if (scr == nullptr) return PPC_EDEVICE;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(noalloc_setup_kernel, dim3(1), dim3(kNaSetupThreads), 0, st, descs, n, n_invalid, scr);
-    if (n > 0) {
-        const uint32_t waves = 4u * (uint32_t)device_cus(dev);
+    const uint32_t nb = std::max(1u, (n + kNaSetupThreads - 1) / kNaSetupThreads);
+    const uint32_t cus = (uint32_t)device_cus(dev);
+    const uint32_t waves = kNaWavesPerCuSmall * cus;
+    hipLaunchKernelGGL(noalloc_arrays_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, descs, n, scr);
+    hipLaunchKernelGGL(noalloc_count_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, n, cus, scr);
+    hipLaunchKernelGGL(noalloc_items_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, n, n_invalid, scr);
+    if (n > 0)
         hipLaunchKernelGGL(noalloc_batched_kernel<kNaWpb>, dim3((waves + kNaWpb - 1) / kNaWpb), dim3(kNaWpb * kWave),
                            0, st, scr);
-    }
     return hipGetLastError() == hipSuccess ? PPC_OK : PPC_EDEVICE;
 }
 
