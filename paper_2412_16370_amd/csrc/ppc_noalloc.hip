@@ -11,11 +11,11 @@
 //   [256, 256 + 64 * 2^16)        one ArrayInfo per array (at most 2^16)
 //   [.., + 64 * 256)              per-block partial sums of the setup kernels
 //   [.., + 16 * 2^18)             work items (at most 2^18), largest first
-// Four launches per call: three setup kernels over the descriptors, one
-// thread per array (array table and block sums; item size and item counts;
-// item offsets and the items themselves), then the persistent kernel that
-// walks the items.  Nothing is allocated and nothing is copied from the
-// host, so the call can be captured.
+// Setup on the device, one thread per array: for at most 256 arrays one
+// kernel, else three (array table and block sums; walk grid, item size and
+// per-block item counts; item offsets and the items themselves), then the
+// persistent kernel that walks the items.  Nothing is allocated and nothing
+// is copied from the host, so the call can be captured.
 //
 // Each GPU holds one copy of `scratch` for as long as the process runs;
 // calls that overlap on one GPU (different streams, or several host
@@ -49,12 +49,18 @@ constexpr uint32_t kNaMaxItemTilesBal = 256;
 // Shorter items (one per array at most: its tiles past the last whole item,
 // or only its head/tail bytes) go into buckets by the bit length of their
 // tile count, clamped to kNaBuckets - 1, and are laid out largest bucket
-// first: the largest-first order of the plan, without a sort.  Items of at
-// most 3 tiles (buckets below kNaFirstSingle) are handed out kNaGroup per
-// ticket; the rest one per ticket.
+// first: the largest-first order of the plan, without a sort.  The whole
+// items and each bucket form one segment of the table.  A ticket hands out
+// a run of items of one segment, a power of two of them: as many as make
+// about kNaGroupTiles tiles at the segment's smallest item size (32 items
+// of at most one tile, 8 of 4-7 tiles, one of 32 or more), so that short
+// items do not queue one by one on the cursor; but at most items / walking
+// waves, so that a small batch still spreads over every wave, and halved
+// while the segment would make between one and two tickets per wave (the
+// second round would leave most waves idle).
 constexpr int kNaBuckets = 10;
-constexpr int kNaFirstSingle = 3;  // bit length 3: 4 tiles or more
-constexpr uint32_t kNaGroup = 16;
+constexpr int kNaSegments = kNaBuckets + 1;  // [0]: whole items, [1 + (kNaBuckets - 1 - b)]: bucket b
+constexpr uint32_t kNaGroupTiles = 32;
 constexpr int kNaSetupThreads = 256;
 constexpr uint32_t kNaMaxBlocks = kNaMaxArrays / kNaSetupThreads;
 static_assert(kNaMaxBlocks <= (uint32_t)kNaSetupThreads, "one thread per setup block in the block scans");
@@ -69,16 +75,23 @@ constexpr uint32_t kNaWavesPerCu = 4;
 constexpr uint32_t kNaWavesPerCuSmall = 8;
 constexpr uint64_t kNaShortMeanTiles = 4;
 
+// One segment of the item table: items [item0, item0 + count), handed out
+// `group` per ticket from ticket ticket0 on.
+struct NaSegment {
+    uint32_t ticket0, item0, count, group;
+};
+
 struct NaHeader {
     uint32_t cursor;     // tickets handed out after each wave's first
-    uint32_t n_single;   // whole items, then shorter ones of >= 4 tiles: one per ticket
-    uint32_t n_items;    // all items; those past n_single go kNaGroup per ticket
-    uint32_t n_tickets;  // n_single + ceil((n_items - n_single) / kNaGroup)
+    uint32_t n_items;    // all items
+    uint32_t n_tickets;  // sum over segments of ceil(count / group)
     uint32_t tiles_per_item;
     uint32_t ok;         // 1: every descriptor valid and the items fit the table
     uint32_t n_bad;      // invalid descriptors
     uint32_t waves;      // waves of the walk that take tickets
-    uint32_t reserved[56];
+    uint32_t reserved0;
+    NaSegment seg[kNaSegments];
+    uint32_t reserved[12];
 };
 static_assert(sizeof(NaHeader) == 256, "header size");
 
@@ -138,7 +151,142 @@ __device__ __forceinline__ void na_count_items(const ArrayInfo &ai, uint32_t P, 
     if (rest != 0u || (ai.n_tiles == 0u && edges)) ++cnt[na_bucket(rest)];
 }
 
-// Setup 1, thread i <-> array i: validates the descriptor, writes the array
+// ---- setup steps (each kernel below is a composition of them) -----------
+
+// Thread i <-> array i: validates descriptor i and writes its table entry
+// (an invalid one gets an empty entry).  Returns the entry; *bad and *tiles
+// receive whether it was invalid and its tile count.
+__device__ __forceinline__ ArrayInfo na_array_entry(const ppc_desc *__restrict__ descs, uint32_t n, uint32_t i,
+                                                    ArrayInfo *arrays, uint32_t &bad, uint64_t &tiles) {
+    ArrayInfo ai{};
+    bad = 0u;
+    tiles = 0u;
+    if (i < n) {
+        const ppc_desc d = descs[i];
+        if (d.reserved != 0u || !make_array_info(ai, d.buf, d.nbytes, d.counts, d.width)) {
+            bad = 1u;
+            ai = ArrayInfo{};
+        }
+        arrays[i] = ai;
+        tiles = ai.n_tiles;
+    }
+    return ai;
+}
+
+struct NaChoice {
+    uint32_t waves;  // walking waves
+    uint32_t P;      // tiles per whole item
+    bool ok;         // every descriptor valid and the items fit the table
+};
+
+// Walking waves and item size for T tiles over n arrays on `cus` CUs.
+__device__ __forceinline__ NaChoice na_choose(uint64_t T, uint32_t n_bad, uint32_t n, uint32_t cus) {
+    // every array gives at most n_tiles/P + 1 items, so P >= T / (kNaMaxItems
+    // - n) keeps the total within the table
+    const uint64_t room = (uint64_t)kNaMaxItems - n;
+    const uint32_t waves = (T < kNaShortMeanTiles * n ? kNaWavesPerCuSmall : kNaWavesPerCu) * max(cus, 1u);
+    const uint64_t per_wave = (uint64_t)kNaItemsPerWave * waves;
+    const uint64_t bal =
+        min(max((T + per_wave - 1) / per_wave, (uint64_t)kNaMinItemTiles), (uint64_t)kNaMaxItemTilesBal);
+    const uint64_t p64 = max(bal, (T + room - 1) / room);
+    return NaChoice{waves, (uint32_t)min(p64, (uint64_t)kMaxItemTiles), n_bad == 0u && p64 <= (uint64_t)kMaxItemTiles};
+}
+
+// Start of each bucket's items in the table (whole items first, then the
+// buckets from the largest down) from the totals; returns the item count.
+__device__ __forceinline__ uint32_t na_layout(const uint32_t (&tot)[kNaBuckets + 1], uint32_t (&base)[kNaBuckets + 1]) {
+    base[kNaBuckets] = 0u;
+    uint32_t next = tot[kNaBuckets];
+    for (int k = kNaBuckets - 1; k >= 0; --k) {
+        base[k] = next;
+        next += tot[k];
+    }
+    return next;
+}
+
+// Writes array i's items at base[k] + at[k] (k: whole items or the rest's
+// bucket); the array's first item carries its head/tail bytes.
+__device__ __forceinline__ void na_write_items(const ArrayInfo &ai, uint32_t i, uint32_t P,
+                                               const uint32_t (&base)[kNaBuckets + 1],
+                                               const uint32_t (&at)[kNaBuckets + 1], WorkItem *items) {
+    const uint32_t edges = ai.edge0_len + ai.edge1_len > 0u ? 1u : 0u;
+    const uint32_t whole = ai.n_tiles / P, rest = ai.n_tiles % P;
+    uint32_t f = base[kNaBuckets] + at[kNaBuckets];
+    for (uint32_t k = 0; k < whole; ++k) items[f++] = WorkItem{i, k * P, (k + 1u) * P, k == 0u ? edges : 0u};
+    if (rest != 0u || (ai.n_tiles == 0u && edges)) {
+        const int b = na_bucket(rest);
+        items[base[b] + at[b]] = WorkItem{i, whole * P, ai.n_tiles, whole == 0u ? edges : 0u};
+    }
+}
+
+// The header for the walk (one thread): segments with their group sizes,
+// ticket count, cursor reset; and the count of invalid descriptors.
+__device__ void na_write_header(NaHeader *h, const uint32_t (&tot)[kNaBuckets + 1],
+                                const uint32_t (&base)[kNaBuckets + 1], uint32_t n_items, const NaChoice &c,
+                                uint32_t n_bad, uint32_t n, uint32_t *n_invalid_out) {
+    // group sizes are powers of two (log2 below), so this needs no division
+    // past the one for the cap
+    const uint32_t nw = max(c.waves, 1u);
+    const uint32_t cap = n_items / nw;
+    const uint32_t lg_cap = cap == 0u ? 0u : bit_length(cap) - 1u;
+    const uint32_t lg_target = bit_length(kNaGroupTiles) - 1u;
+    uint32_t tickets = 0;
+    for (int j = 0; j < kNaSegments; ++j) {
+        const int b = kNaBuckets - j;  // segment j: whole items (b = kNaBuckets), then bucket b
+        // log2 of the segment's smallest item size, rounded down (P is at
+        // least 4; bucket b >= 1 holds items of 2^(b-1) tiles or more)
+        const uint32_t lg_min = b == kNaBuckets ? bit_length(c.P) - 1u : (b == 0 ? 0u : (uint32_t)(b - 1));
+        uint32_t lg_g = min(lg_target > lg_min ? lg_target - lg_min : 0u, lg_cap);
+        const uint32_t count = c.ok ? tot[b] : 0u;
+        while (lg_g > 0u) {
+            const uint32_t k = (count + (1u << lg_g) - 1u) >> lg_g;
+            if (k <= nw || k >= 2u * nw) break;
+            --lg_g;
+        }
+        h->seg[j] = NaSegment{tickets, base[b], count, 1u << lg_g};
+        tickets += (count + (1u << lg_g) - 1u) >> lg_g;
+    }
+    h->cursor = 0u;
+    h->n_items = c.ok ? n_items : 0u;
+    h->n_tickets = tickets;
+    h->tiles_per_item = c.P;
+    h->ok = c.ok ? 1u : 0u;
+    h->n_bad = n_bad;
+    h->waves = c.waves;
+    if (n_invalid_out) *n_invalid_out = c.ok ? 0u : (n_bad ? n_bad : n);
+}
+
+// ---- setup kernels ---------------------------------------------------------
+
+// Batches of at most kNaSetupThreads arrays: one block does every step.
+__global__ __launch_bounds__(kNaSetupThreads) void noalloc_setup_one_block_kernel(const ppc_desc *__restrict__ descs,
+                                                                                  uint32_t n, uint32_t cus,
+                                                                                  uint32_t *n_invalid_out,
+                                                                                  uint8_t *scr) {
+    NaHeader *h = reinterpret_cast<NaHeader *>(scr);
+    ArrayInfo *arrays = reinterpret_cast<ArrayInfo *>(scr + kNaArraysOff);
+    WorkItem *items = reinterpret_cast<WorkItem *>(scr + kNaItemsOff);
+    __shared__ uint64_t lds64[1][kNaSetupThreads];
+    __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupThreads];
+    const uint32_t i = threadIdx.x;
+    uint32_t bad[1];
+    uint64_t tiles[1];
+    const ArrayInfo ai = na_array_entry(descs, n, i, arrays, bad[0], tiles[0]);
+    uint32_t n_bad[1];
+    uint64_t T[1];
+    block_exclusive_scan<uint32_t, 1>(bad, lds32, n_bad);
+    block_exclusive_scan<uint64_t, 1>(tiles, lds64, T);
+    const NaChoice c = na_choose(T[0], n_bad[0], n, cus);
+    uint32_t cnt[kNaBuckets + 1] = {0};
+    if (c.ok && i < n) na_count_items(ai, c.P, cnt);
+    uint32_t tot[kNaBuckets + 1], base[kNaBuckets + 1];
+    block_exclusive_scan<uint32_t, kNaBuckets + 1>(cnt, lds32, tot);
+    const uint32_t n_items = na_layout(tot, base);
+    if (c.ok && i < n) na_write_items(ai, i, c.P, base, cnt, items);
+    if (i == 0) na_write_header(h, tot, base, n_items, c, n_bad[0], n, n_invalid_out);
+}
+
+// Larger batches, three kernels.  Setup 1, thread i <-> array i: the array
 // table entry, and the block's sums of invalid descriptors and tiles.
 __global__ __launch_bounds__(kNaSetupThreads) void noalloc_arrays_kernel(const ppc_desc *__restrict__ descs,
                                                                          uint32_t n, uint8_t *scr) {
@@ -146,19 +294,9 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_arrays_kernel(const p
     NaPartial *part = reinterpret_cast<NaPartial *>(scr + kNaPartOff);
     __shared__ uint64_t lds64[1][kNaSetupThreads];
     __shared__ uint32_t lds32[1][kNaSetupThreads];
-    const uint32_t i = blockIdx.x * kNaSetupThreads + threadIdx.x;
-    uint32_t bad[1] = {0};
-    uint64_t tiles[1] = {0};
-    if (i < n) {
-        const ppc_desc d = descs[i];
-        ArrayInfo ai;
-        if (d.reserved != 0u || !make_array_info(ai, d.buf, d.nbytes, d.counts, d.width)) {
-            bad[0] = 1u;
-            ai = ArrayInfo{};
-        }
-        arrays[i] = ai;
-        tiles[0] = ai.n_tiles;
-    }
+    uint32_t bad[1];
+    uint64_t tiles[1];
+    (void)na_array_entry(descs, n, blockIdx.x * kNaSetupThreads + threadIdx.x, arrays, bad[0], tiles[0]);
     uint32_t sb[1];
     uint64_t st[1];
     block_exclusive_scan<uint32_t, 1>(bad, lds32, sb);
@@ -170,9 +308,9 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_arrays_kernel(const p
 }
 
 // Setup 2: every block sums the first kernel's block sums (the same totals
-// in every block), picks the walking waves (of `cus` CUs) and the tiles per
-// whole item, and writes its own item counts per bucket; block 0 records the
-// choices in the header.
+// in every block), makes the same choice of walking waves and item size,
+// and writes its own item counts per bucket; block 0 records the choice in
+// the header.
 __global__ __launch_bounds__(kNaSetupThreads) void noalloc_count_kernel(uint32_t n, uint32_t cus, uint8_t *scr) {
     NaHeader *h = reinterpret_cast<NaHeader *>(scr);
     const ArrayInfo *arrays = reinterpret_cast<const ArrayInfo *>(scr + kNaArraysOff);
@@ -183,41 +321,29 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_count_kernel(uint32_t
     uint32_t bad[1] = {tid < nb ? part[tid].bad : 0u};
     uint64_t tiles[1] = {tid < nb ? part[tid].tiles : 0ull};
     uint32_t n_bad[1];
-    uint64_t n_tiles[1];
+    uint64_t T[1];
     block_exclusive_scan<uint32_t, 1>(bad, lds32, n_bad);
-    block_exclusive_scan<uint64_t, 1>(tiles, lds64, n_tiles);
-
-    // every array gives at most n_tiles/P + 1 items, so P >= n_tiles /
-    // (kNaMaxItems - n) keeps the total within the table
-    const uint64_t T = n_tiles[0], room = (uint64_t)kNaMaxItems - n;
-    const uint32_t waves = (T < kNaShortMeanTiles * n ? kNaWavesPerCuSmall : kNaWavesPerCu) * max(cus, 1u);
-    const uint64_t per_wave = (uint64_t)kNaItemsPerWave * waves;
-    const uint64_t bal = min(max((T + per_wave - 1) / per_wave, (uint64_t)kNaMinItemTiles), (uint64_t)kNaMaxItemTilesBal);
-    const uint64_t p64 = max(bal, (T + room - 1) / room);
-    const bool ok = n_bad[0] == 0u && p64 <= (uint64_t)kMaxItemTiles;
-    const uint32_t P = (uint32_t)min(p64, (uint64_t)kMaxItemTiles);
-
+    block_exclusive_scan<uint64_t, 1>(tiles, lds64, T);
+    const NaChoice c = na_choose(T[0], n_bad[0], n, cus);
     const uint32_t i = blockIdx.x * kNaSetupThreads + tid;
     uint32_t cnt[kNaBuckets + 1] = {0};
-    if (ok && i < n) na_count_items(arrays[i], P, cnt);
+    if (c.ok && i < n) na_count_items(arrays[i], c.P, cnt);
     uint32_t tot[kNaBuckets + 1];
     block_exclusive_scan<uint32_t, kNaBuckets + 1>(cnt, lds32, tot);
     if (tid == 0) {
         for (int k = 0; k <= kNaBuckets; ++k) part[blockIdx.x].cnt[k] = tot[k];
         if (blockIdx.x == 0) {
-            h->tiles_per_item = P;
-            h->ok = ok ? 1u : 0u;
+            h->tiles_per_item = c.P;
+            h->ok = c.ok ? 1u : 0u;
             h->n_bad = n_bad[0];
-            h->waves = waves;
+            h->waves = c.waves;
         }
     }
 }
 
 // Setup 3: every block scans the blocks' item counts (the same layout in
-// every block): whole items first, then the buckets from the largest down;
-// within each, blocks in order and arrays in order.  Then thread i writes
-// array i's items; an array's first item carries its head/tail bytes.
-// Block 0 completes the header and reports invalid descriptors.
+// every block; within each bucket, blocks in order and arrays in order),
+// then thread i writes array i's items.  Block 0 completes the header.
 __global__ __launch_bounds__(kNaSetupThreads) void noalloc_items_kernel(uint32_t n, uint32_t *n_invalid_out,
                                                                         uint8_t *scr) {
     NaHeader *h = reinterpret_cast<NaHeader *>(scr);
@@ -227,73 +353,72 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_items_kernel(uint32_t
     __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupThreads];
     __shared__ uint32_t blk_base[kNaBuckets + 1];
     const uint32_t tid = threadIdx.x, nb = gridDim.x;
-    const uint32_t P = h->tiles_per_item;
-    const bool ok = h->ok != 0u;
+    const NaChoice c{h->waves, h->tiles_per_item, h->ok != 0u};
+    const uint32_t n_bad = h->n_bad;
 
-    uint32_t blk[kNaBuckets + 1], tot[kNaBuckets + 1];
+    uint32_t blk[kNaBuckets + 1], tot[kNaBuckets + 1], base[kNaBuckets + 1];
 #pragma unroll
     for (int k = 0; k <= kNaBuckets; ++k) blk[k] = tid < nb ? part[tid].cnt[k] : 0u;
     block_exclusive_scan<uint32_t, kNaBuckets + 1>(blk, lds32, tot);
     if (tid == blockIdx.x)
         for (int k = 0; k <= kNaBuckets; ++k) blk_base[k] = blk[k];
-    uint32_t base[kNaBuckets + 1];
-    base[kNaBuckets] = 0u;
-    uint32_t next = tot[kNaBuckets];
-    for (int k = kNaBuckets - 1; k >= 0; --k) {
-        base[k] = next;
-        next += tot[k];
-    }
-    const uint32_t n_items = next;
-    const uint32_t n_single = base[kNaFirstSingle] + tot[kNaFirstSingle];
+    const uint32_t n_items = na_layout(tot, base);
 
     const uint32_t i = blockIdx.x * kNaSetupThreads + tid;
     uint32_t cnt[kNaBuckets + 1] = {0};
-    if (ok && i < n) na_count_items(arrays[i], P, cnt);
+    if (c.ok && i < n) na_count_items(arrays[i], c.P, cnt);
     uint32_t unused[kNaBuckets + 1];
     block_exclusive_scan<uint32_t, kNaBuckets + 1>(cnt, lds32, unused);  // also orders blk_base
-    if (ok && i < n) {
-        const ArrayInfo &ai = arrays[i];
-        const uint32_t edges = ai.edge0_len + ai.edge1_len > 0u ? 1u : 0u;
-        const uint32_t whole = ai.n_tiles / P, rest = ai.n_tiles % P;
-        uint32_t f = base[kNaBuckets] + blk_base[kNaBuckets] + cnt[kNaBuckets];
-        for (uint32_t k = 0; k < whole; ++k) items[f++] = WorkItem{i, k * P, (k + 1u) * P, k == 0u ? edges : 0u};
-        if (rest != 0u || (ai.n_tiles == 0u && edges)) {
-            const int b = na_bucket(rest);
-            items[base[b] + blk_base[b] + cnt[b]] = WorkItem{i, whole * P, ai.n_tiles, whole == 0u ? edges : 0u};
-        }
+    if (c.ok && i < n) {
+        uint32_t at[kNaBuckets + 1];
+#pragma unroll
+        for (int k = 0; k <= kNaBuckets; ++k) at[k] = blk_base[k] + cnt[k];
+        na_write_items(arrays[i], i, c.P, base, at, items);
     }
-    if (blockIdx.x == 0 && tid == 0) {
-        h->cursor = 0u;
-        h->n_single = ok ? n_single : 0u;
-        h->n_items = ok ? n_items : 0u;
-        h->n_tickets = ok ? n_single + (n_items - n_single + kNaGroup - 1u) / kNaGroup : 0u;
-        if (n_invalid_out) *n_invalid_out = ok ? 0u : (h->n_bad ? h->n_bad : n);
-    }
+    if (blockIdx.x == 0 && tid == 0) na_write_header(h, tot, base, n_items, c, n_bad, n, n_invalid_out);
 }
 
 // Persistent walk: of the launched waves, the first `waves` (from the
 // header) walk and the rest exit.  Wave g starts with ticket g, then takes
-// tickets from the cursor once its current one is done.  Ticket
-// t < n_single is item t; later tickets are runs of kNaGroup items.
+// tickets from the cursor once its current one is done; if there are no
+// more tickets than walking waves, the first is the only one and the
+// cursor is not touched (otherwise every wave's last atomic, which finds
+// nothing, queues on the one address at the same moment).  Ticket t
+// belongs to the last segment whose first ticket is at most t, and stands
+// for the run of that segment's items it numbers.
 template <int WPB>
 __global__ __launch_bounds__(WPB *kWave) void noalloc_batched_kernel(uint8_t *scr) {
     NaHeader *h = reinterpret_cast<NaHeader *>(scr);
     const ArrayInfo *arrays = reinterpret_cast<const ArrayInfo *>(scr + kNaArraysOff);
     const WorkItem *items = reinterpret_cast<const WorkItem *>(scr + kNaItemsOff);
     const uint32_t n_tickets = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->n_tickets);
-    const uint32_t n_single = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->n_single);
-    const uint32_t n_items = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->n_items);
     const uint32_t nw = min((uint32_t)__builtin_amdgcn_readfirstlane((int)h->waves), gridDim.x * WPB);
     uint32_t t = blockIdx.x * WPB + wave_in_block();
     if (t >= nw) return;
+    // the segment table, read once (the loop's atomics would otherwise make
+    // the compiler reload it for every ticket)
+    uint32_t s_t0[kNaSegments], s_i0[kNaSegments], s_end[kNaSegments], s_g[kNaSegments];
+#pragma unroll
+    for (int j = 0; j < kNaSegments; ++j) {
+        s_t0[j] = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->seg[j].ticket0);
+        s_i0[j] = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->seg[j].item0);
+        s_end[j] = s_i0[j] + (uint32_t)__builtin_amdgcn_readfirstlane((int)h->seg[j].count);
+        s_g[j] = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->seg[j].group);
+    }
     while (t < n_tickets) {
-        if (t < n_single) {
-            run_item(arrays, items[t]);
-        } else {
-            const uint32_t i0 = n_single + (t - n_single) * kNaGroup;
-            const uint32_t i1 = min(i0 + kNaGroup, n_items);
-            for (uint32_t i = i0; i < i1; ++i) run_item(arrays, items[i]);
+        uint32_t tk0 = 0, it0 = 0, end = 0, g = 1;
+#pragma unroll
+        for (int j = 0; j < kNaSegments; ++j) {
+            const bool in = t >= s_t0[j];
+            tk0 = in ? s_t0[j] : tk0;
+            it0 = in ? s_i0[j] : it0;
+            end = in ? s_end[j] : end;
+            g = in ? s_g[j] : g;
         }
+        const uint32_t i0 = it0 + (t - tk0) * g;
+        const uint32_t i1 = min(i0 + g, end);
+        for (uint32_t i = i0; i < i1; ++i) run_item(arrays, items[i]);
+        if (n_tickets <= nw) break;
         uint32_t ticket = 0;
         if (__lane_id() == 0u) ticket = atomicAdd(&h->cursor, 1u);
         t = nw + (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
@@ -331,12 +456,17 @@ ppc_status ppc_batch_noalloc(const ppc_desc *descs, uint32_t n, uint32_t *n_inva
     uint8_t *scr = noalloc_scratch(dev);
     if (scr == nullptr) return PPC_EDEVICE;
     hipStream_t st = (hipStream_t)stream;
-    const uint32_t nb = std::max(1u, (n + kNaSetupThreads - 1) / kNaSetupThreads);
+    const uint32_t nb = (n + kNaSetupThreads - 1) / kNaSetupThreads;
     const uint32_t cus = (uint32_t)device_cus(dev);
     const uint32_t waves = kNaWavesPerCuSmall * cus;
-    hipLaunchKernelGGL(noalloc_arrays_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, descs, n, scr);
-    hipLaunchKernelGGL(noalloc_count_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, n, cus, scr);
-    hipLaunchKernelGGL(noalloc_items_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, n, n_invalid, scr);
+    if (nb <= 1) {
+        hipLaunchKernelGGL(noalloc_setup_one_block_kernel, dim3(1), dim3(kNaSetupThreads), 0, st, descs, n, cus,
+                           n_invalid, scr);
+    } else {
+        hipLaunchKernelGGL(noalloc_arrays_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, descs, n, scr);
+        hipLaunchKernelGGL(noalloc_count_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, n, cus, scr);
+        hipLaunchKernelGGL(noalloc_items_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, n, n_invalid, scr);
+    }
     if (n > 0)
         hipLaunchKernelGGL(noalloc_batched_kernel<kNaWpb>, dim3((waves + kNaWpb - 1) / kNaWpb), dim3(kNaWpb * kWave),
                            0, st, scr);

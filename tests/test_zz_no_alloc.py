@@ -167,6 +167,18 @@ def test_maximum_array_count(ppc):
     check_against_oracle(got, pool, spec)
 
 
+def test_one_block_and_grid_setup_boundary(ppc):
+    """255 and 256 arrays take the one-block setup, 257 the three grid-wide
+    setup kernels; three calls in a row, each against the plan and the
+    oracle (short and long arrays, unaligned starts)."""
+    for k, n in enumerate((255, 256, 257)):
+        spec = synth.batch_spec(n, seed=50 + k, lo=16, hi=2 * MiB, start_jitter=64)
+        pool = make_pool(spec, seed=50 + k)
+        got = noalloc_counts(ppc, pool, spec)
+        assert np.array_equal(got, plan_counts(ppc, pool, spec))
+        check_against_oracle(got, pool, spec)
+
+
 def test_captured_in_a_graph_and_replayed(ppc):
     """The call records into a HIP graph (torch.cuda.CUDAGraph capturing on
     its own stream): every replay adds exactly one batch's counts, with an
