@@ -52,7 +52,10 @@ __global__ void prologue_kernel(uint32_t *cursor, unsigned long long *clear, uin
 // for the whole of the current one, and near the end short groups then
 // wait behind long ones while other waves are idle (10,000-array mix, 4 MiB
 // items: a ~190 us tail, 6.6 against 6.9 TB/s).  The ticket's latency is
-// small against a group (at least 16 tiles).
+// small against a group (at least 16 tiles).  If there are no more groups
+// than waves, a wave's first group is its only one and the cursor is not
+// touched: otherwise every wave's last atomic, which finds nothing, would
+// queue on the one address at the same moment.
 __device__ __forceinline__ void run_groups(const ArrayInfo *__restrict__ arrays, const WorkItem *__restrict__ items,
                                            const uint32_t *__restrict__ groups, uint32_t n_groups, uint32_t *cursor,
                                            uint32_t gw, uint32_t nw) {
@@ -61,6 +64,7 @@ __device__ __forceinline__ void run_groups(const ArrayInfo *__restrict__ arrays,
     while (grp < n_groups) {
         const uint32_t i0 = groups[grp], i1 = groups[grp + 1];
         for (uint32_t i = i0; i < i1; ++i) run_item(arrays, items[i]);
+        if (n_groups <= nw) break;
         uint32_t ticket = 0;
         if (lane == 0) ticket = atomicAdd(cursor, 1u);
         grp = nw + (uint32_t)__builtin_amdgcn_readfirstlane((int)ticket);
