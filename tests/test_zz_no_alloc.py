@@ -179,6 +179,51 @@ def test_one_block_and_grid_setup_boundary(ppc):
         check_against_oracle(got, pool, spec)
 
 
+def random_batch(rng, kind, n_tiles=(0, 0)):
+    """A seeded batch of one of three shapes: 'mix' (1-700 arrays, lengths
+    log-uniform up to 2 MiB, some empty), 'tiles' (n arrays of k whole tiles
+    less 0-63 bytes, so that the items share a bucket and tickets group
+    several of them), 'edge' (thousands of arrays of 0-40 bytes: head/tail
+    items only)."""
+    if kind == "mix":
+        n = int(rng.integers(1, 700))
+        lengths = np.exp(rng.uniform(0.0, np.log(2 * MiB), size=n)).astype(np.int64)
+        lengths[rng.random(n) < 0.05] = 0
+    elif kind == "tiles":
+        n, k = n_tiles
+        lengths = k * 16384 - rng.integers(0, 64, size=n)
+    else:
+        n = int(rng.integers(2000, 6000))
+        lengths = rng.integers(0, 41, size=n)
+    widths = rng.choice(np.array([8, 16, 32, 64]), size=n)
+    jitter = rng.integers(0, 64, size=n)
+    offsets = np.empty(n, dtype=np.int64)
+    pos = 0
+    for i in range(n):
+        pos = (pos + 255) // 256 * 256
+        offsets[i] = pos + jitter[i]
+        pos = int(offsets[i] + lengths[i])
+    return dict(offsets=offsets, lengths=lengths.astype(np.int64), widths=widths.astype(np.int64),
+                p=rng.uniform(0.0, 1.0, size=n), pool_bytes=pos + 256)
+
+
+def test_random_batches_match_the_plan_and_the_oracle(ppc):
+    """Twelve seeded batches of the three shapes, one call after another on
+    the shared scratch: every array equals the plan's and the oracle's.  The
+    'tiles' batches (n arrays of k tiles) take the cursor-free walk (300 x 1),
+    and groups of two or one halved from twice that (3,000 x 4, 5,000 x 1,
+    10,000 x 2)."""
+    rng = np.random.default_rng(60)
+    tiles = iter([(300, 1), (3000, 4), (10000, 2), (5000, 1)])
+    for b, kind in enumerate(["mix"] * 6 + ["tiles"] * 4 + ["edge"] * 2):
+        spec = random_batch(rng, kind, next(tiles) if kind == "tiles" else (0, 0))
+        print("random batch %d (%s): %d arrays" % (b, kind, len(spec["lengths"])), flush=True)
+        pool = make_pool(spec, seed=60 + b)
+        got = noalloc_counts(ppc, pool, spec)
+        assert np.array_equal(got, plan_counts(ppc, pool, spec)), "batch %d (%s)" % (b, kind)
+        check_against_oracle(got, pool, spec)
+
+
 def test_captured_in_a_graph_and_replayed(ppc):
     """The call records into a HIP graph (torch.cuda.CUDAGraph capturing on
     its own stream): every replay adds exactly one batch's counts, with an
