@@ -160,7 +160,7 @@ void sort_items_lpt(std::vector<WorkItem> &items) {
     });
 }
 
-std::vector<uint32_t> build_groups(const std::vector<WorkItem> &items, uint32_t waves) {
+std::vector<uint32_t> build_groups(const std::vector<WorkItem> &items, uint32_t waves, uint32_t cost_limit) {
     const uint64_t spread = waves ? (items.size() + waves - 1) / waves : (uint64_t)kGroupMax;  // 0: no cap
     const uint32_t max_items = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kGroupMax, spread));
     std::vector<uint32_t> starts;
@@ -170,7 +170,7 @@ std::vector<uint32_t> build_groups(const std::vector<WorkItem> &items, uint32_t 
         if (count == 0) starts.push_back(i);
         cost += (items[i].tile1 - items[i].tile0) + 1u;
         ++count;
-        if (cost >= kGroupCost || count >= max_items) {
+        if (cost >= cost_limit || count >= max_items) {
             cost = 0;
             count = 0;
         }
@@ -287,7 +287,7 @@ std::vector<WorkItem> build_items(const std::vector<ArrayInfo> &arrays, uint32_t
 ppc_status time_candidate(const ArrayInfo *tune_arrays_dev, const std::vector<ArrayInfo> &arrays, uint32_t p,
                           uint32_t waves, uint32_t *cursor_dev, hipStream_t st, int reps, float &ms_out) {
     std::vector<WorkItem> items = build_items(arrays, p);
-    std::vector<uint32_t> groups = build_groups(items, 0u);
+    std::vector<uint32_t> groups = build_groups(items, waves, kPlanGroupCost);
     WorkItem *items_dev = nullptr;
     uint32_t *groups_dev = nullptr;
     if (!items.empty() && hipMalloc(&items_dev, items.size() * sizeof(WorkItem)) != hipSuccess) return PPC_ENOMEM;
@@ -446,7 +446,7 @@ ppc_status ppc_plan_create(ppc_plan **out, const ppc_desc *descs, size_t n, cons
     p->tiles_per_item = std::min(tp, kMaxItemTiles);
     p->waves = wv;
     std::vector<WorkItem> items = build_items(p->arrays, p->tiles_per_item);
-    std::vector<uint32_t> groups = build_groups(items, 0u);
+    std::vector<uint32_t> groups = build_groups(items, p->waves, kPlanGroupCost);
     p->n_items = (uint32_t)items.size();
     p->n_groups = (uint32_t)groups.size() - 1u;
     if ((n > 0 && hipMalloc(&p->arrays_dev, n * sizeof(ArrayInfo)) != hipSuccess) ||

@@ -111,17 +111,18 @@ void sort_items_lpt(std::vector<WorkItem> &items);
 
 // Groups consecutive items (in LPT order) into units of work handed out by
 // one ticket: a group closes when its cost (tiles + 1 per item for the
-// per-item reduction) reaches kGroupCost, or when it holds kGroupMax items
-// or, if `waves` is not 0, ceil(items / waves) items, whichever is fewer.
-// So a large item is a group of its own and tiny ones travel together.  The
-// server passes its grid size, so that a small batch spreads over every
-// wave, each with one group and no ticket (p99 at half load 190-200 us
-// instead of 220-320 us); plans pass 0 (10,000 tiny arrays: 38 us per run
-// with groups of 8 items on ~1,250 waves, 44 us spread over 2,048).
-// Returns the n_groups + 1 start indices.
-constexpr uint32_t kGroupCost = 16;
+// per-item reduction) reaches `cost`, or when it holds kGroupMax items or,
+// if `waves` is not 0, ceil(items / waves) items, whichever is fewer.  So a
+// large item is a group of its own and tiny ones travel together, and a
+// batch of few items spreads over every wave, each with one group and no
+// ticket.  The server uses kServedGroupCost (p99 at half load 190-200 us
+// spread over its grid, instead of 220-320 us); plans kPlanGroupCost
+// (65,536 arrays of 1 KiB: 55 against 121 us per run with cost 16; arrays
+// of 64 KiB or more: the same).  Returns the n_groups + 1 start indices.
+constexpr uint32_t kServedGroupCost = 16;
+constexpr uint32_t kPlanGroupCost = 32;
 constexpr uint32_t kGroupMax = 64;
-std::vector<uint32_t> build_groups(const std::vector<WorkItem> &items, uint32_t waves);
+std::vector<uint32_t> build_groups(const std::vector<WorkItem> &items, uint32_t waves, uint32_t cost);
 
 // Enqueues the prologue (cursor reset, and a clear of n_clear counters at
 // `clear` if given) and the persistent kernel on `st`.  Wave g of the grid

@@ -184,7 +184,7 @@ void dispatch(ppc_server *s) {
             ++n;
         }
         sort_items_lpt(items);
-        const std::vector<uint32_t> groups = build_groups(items, s->cfg.waves);
+        const std::vector<uint32_t> groups = build_groups(items, s->cfg.waves, kServedGroupCost);
         std::memcpy(l.stage_host + s->items_off, items.data(), items.size() * sizeof(WorkItem));
         std::memcpy(l.stage_host + s->groups_off, groups.data(), groups.size() * sizeof(uint32_t));
         BatchHeader *h = reinterpret_cast<BatchHeader *>(l.stage_host);
