@@ -56,6 +56,10 @@ __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
 constexpr int kMaxK1 = 6;
 constexpr uint32_t kSegTiles = (1u << kMaxK1) - 1u;  // 63 tiles = 1008 KiB per wave
 constexpr int kPlanes = 4 + kMaxK1;
+// A wave whose only data is a partial tile of at most kFewChunks chunks per
+// lane (and an edge chunk) skips the top counter: 14 + 1 inputs per bit fit
+// the four carry-save planes.
+constexpr uint32_t kFewChunks = 14;
 
 struct Planes {
     uint4 a1, a2, a4, a8;
@@ -358,6 +362,34 @@ __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t
             p[0] = make_uint4(v.x ^ edge.x, v.y ^ edge.y, v.z ^ edge.z, v.w ^ edge.w);
             p[1] = make_uint4(v.x & edge.x, v.y & edge.y, v.z & edge.z, v.w & edge.w);
             return wave_position_counts(p, 2u);
+        }
+        // A partial tile alone, of k <= kFewChunks chunks per lane: with the
+        // edge chunk a bit sees at most 15 inputs, so the carry-save network
+        // leaves the lane's count in binary in its four planes (its carry-out
+        // is zero), and only the low bit_length(k + 1) planes can be
+        // non-zero.  The top counter and the zero planes are skipped: two to
+        // four planes go into the reduction instead of five.
+        if (n_mine == 0 && partial_chunks <= (uint64_t)kFewChunks * kWave) {
+            const uint32_t k = (uint32_t)((partial_chunks + kWave - 1u) / kWave);
+            const uint64_t base = (uint64_t)n_full * kTileChunks + lane;
+            uint4 v[kLoadsPerTile];
+#pragma unroll
+            for (int j = 0; j < kLoadsPerTile; ++j) {
+                const uint64_t idx = base + (uint64_t)j * kWave;
+                v[j] = (uint32_t)j < k && idx < n_chunks ? body[idx] : zero4();
+            }
+            Planes pl;
+            pl.a1 = edge;
+            pl.a2 = pl.a4 = pl.a8 = zero4();
+            (void)pl.csa16(v);
+            uint4 p[kPlanes];
+            p[0] = pl.a1;
+            p[1] = pl.a2;
+            p[2] = pl.a4;
+            p[3] = pl.a8;
+#pragma unroll
+            for (int e = 4; e < kPlanes; ++e) p[e] = zero4();
+            return wave_position_counts(p, bit_length(k + (has_edge ? 1u : 0u)));
         }
     }
     Planes pl;

@@ -237,6 +237,41 @@ def test_every_short_length_and_offset_in_one_plan(ppc, w):
     assert np.array_equal(buf.cpu().numpy(), host)  # input untouched
 
 
+@pytest.mark.parametrize("w", (8, 16, 32, 64))
+def test_partial_tiles_of_4_to_16_KiB(ppc, w):
+    """Arrays of 4,080..16,392 bytes (every 8th length) at start offsets 0, 3,
+    16 and 63: no whole tile, a partial tile of 4..16 chunks per lane (the
+    short partial-tile walk up to 14, the full one above), counted by one
+    plan and, every 17th length, by plain calls; every count equals the
+    oracle's."""
+    lo, hi, max_len = 64, 128, 16392
+    offsets, lengths = (0, 3, 16, 63), list(range(4080, max_len + 1, 8))
+    region = synth.random_bytes(max_len + 64, seed=70 + w)
+    host = np.concatenate([np.full(lo, 0xFF, np.uint8), region, np.full(hi, 0xFF, np.uint8)])
+    buf = torch.from_numpy(host).to(dev())
+    starts = [lo + o for o in offsets for _ in lengths]
+    lens = [n for _ in offsets for n in lengths]
+    rows = len(lens)
+    want = oracle.pospopcnt_ranges(host, starts, lens, [w] * rows)
+    counts = torch.zeros((rows, w), dtype=torch.int64, device=dev())
+    base, cbase = buf.data_ptr(), counts.data_ptr()
+    descs = ppc.make_descs([base + s for s in starts], lens, [cbase + r * w * 8 for r in range(rows)], [w] * rows)
+    plan = ppc.ppc_plan_create(descs, rows, ppc.ppc_plan_opts(16, 0, 0, 1, 0))
+    try:
+        ppc.ppc_plan_run(plan)
+        torch.cuda.synchronize()
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    got = ppc.counts_to_numpy(counts).reshape(rows, w)
+    for r in range(rows):
+        assert np.array_equal(got[r], want[r]), "plan: start %d, length %d" % (starts[r], lens[r])
+    one = torch.zeros(w, dtype=torch.int64, device=dev())
+    for r in range(0, rows, 17):
+        one.zero_()
+        ppc.ppc_pospopcnt(w, one, buf[starts[r]:starts[r] + lens[r]])
+        assert np.array_equal(ppc.counts_to_numpy(one), want[r]), "plain: start %d, length %d" % (starts[r], lens[r])
+
+
 @pytest.mark.parametrize("tiles_per_item", (0, 1 << 18))
 def test_arrays_beyond_4GiB_in_one_plan(ppc, tiles_per_item, tmp_path, monkeypatch):
     """Maximum sizes in the batched form: a 5 GiB + 13-byte array (over 2^18
