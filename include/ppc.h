@@ -218,7 +218,7 @@ ppc_status ppc_plan_destroy(ppc_plan *plan);
  * and race: order them on one stream.  PPC_EDEVICE if a launch fails.
  * ---------------------------------------------------------------------- */
 #define PPC_NOALLOC_MAX_ARRAYS 65536u
-#define PPC_NOALLOC_SCRATCH_BYTES (256u + 64u * 65536u + 64u * 256u + 16u * 262144u)
+#define PPC_NOALLOC_SCRATCH_BYTES (512u + 64u * 65536u + 128u * 256u + 16u * 262144u)
 
 ppc_status ppc_batch_noalloc(const ppc_desc *descs, uint32_t n, uint32_t *n_invalid, void *stream);
 

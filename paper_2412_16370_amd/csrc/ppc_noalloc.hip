@@ -47,8 +47,8 @@ constexpr uint32_t kNaItemsPerWave = 1;
 constexpr uint32_t kNaMinItemTiles = 4;
 constexpr uint32_t kNaMaxItemTilesBal = 256;
 // Shorter items (one per array at most: its tiles past the last whole item,
-// or only its head/tail bytes) go into buckets by the bit length of their
-// tile count, clamped to kNaBuckets - 1, and are laid out largest bucket
+// or only its head/tail bytes) go into buckets by their tile count (two
+// per bit length, see na_bucket), and are laid out largest bucket
 // first: the largest-first order of the plan, without a sort.  The whole
 // items and each bucket form one segment of the table.  A ticket hands out
 // a run of items of one segment, a power of two of them: as many as make
@@ -58,7 +58,7 @@ constexpr uint32_t kNaMaxItemTilesBal = 256;
 // waves, so that a small batch still spreads over every wave, and halved
 // while the segment would make between one and two tickets per wave (the
 // second round would leave most waves idle).
-constexpr int kNaBuckets = 10;
+constexpr int kNaBuckets = 16;
 constexpr int kNaSegments = kNaBuckets + 1;  // [0]: whole items, [1 + (kNaBuckets - 1 - b)]: bucket b
 constexpr uint32_t kNaGroupTiles = 32;
 constexpr int kNaSetupThreads = 256;
@@ -91,9 +91,9 @@ struct NaHeader {
     uint32_t waves;      // waves of the walk that take tickets
     uint32_t reserved0;
     NaSegment seg[kNaSegments];
-    uint32_t reserved[12];
+    uint32_t reserved[52];
 };
-static_assert(sizeof(NaHeader) == 256, "header size");
+static_assert(sizeof(NaHeader) == 512, "header size");
 
 // Sums of one setup block: its invalid descriptors and tiles (first setup
 // kernel), its item counts per bucket and its whole items (second).
@@ -101,9 +101,9 @@ struct NaPartial {
     uint64_t tiles;
     uint32_t bad;
     uint32_t cnt[kNaBuckets + 1];  // [0, kNaBuckets): buckets, [kNaBuckets]: whole items
-    uint32_t pad[2];
+    uint32_t pad[12];
 };
-static_assert(sizeof(NaPartial) == 64, "partial size");
+static_assert(sizeof(NaPartial) == 128, "partial size");
 
 constexpr size_t kNaArraysOff = sizeof(NaHeader);
 constexpr size_t kNaPartOff = kNaArraysOff + (size_t)kNaMaxArrays * sizeof(ArrayInfo);
@@ -113,45 +113,84 @@ static_assert(kNaScratchBytes == PPC_NOALLOC_SCRATCH_BYTES, "scratch size in the
 
 static __device__ __align__(256) uint8_t scratch[kNaScratchBytes];
 
-// Exclusive prefix sums over the block's threads of K values at once
-// (Hillis-Steele in LDS, one pair of barriers per step for all K); total[k]
-// receives the sum of value k.
+// Exclusive prefix sums over the block's threads of K values at once:
+// within each wave by lane shuffles (six steps, no barrier), then the four
+// wave totals through LDS (`lds` needs kNaSetupThreads / kWave entries per
+// value).  total[k] receives the sum of value k over the block.
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x) {
+    const uint32_t lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const T y = __shfl_up(x, (unsigned)d, kWave);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    return x;
+}
+
 template <typename T, int K>
 __device__ __forceinline__ void block_exclusive_scan(T (&v)[K], T (*lds)[kNaSetupThreads], T (&total)[K]) {
-    const uint32_t tid = threadIdx.x;
+    constexpr int kWaves = kNaSetupThreads / kWave;
+    const uint32_t lane = __lane_id(), wave = threadIdx.x / kWave;
+    T incl[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) lds[k][tid] = v[k];
+    for (int k = 0; k < K; ++k) incl[k] = wave_inclusive_scan(v[k]);
+    if (lane == kWave - 1)
+#pragma unroll
+        for (int k = 0; k < K; ++k) lds[k][wave] = incl[k];
     __syncthreads();
-    for (uint32_t d = 1; d < (uint32_t)kNaSetupThreads; d <<= 1) {
-        T add[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) add[k] = tid >= d ? lds[k][tid - d] : T(0);
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < K; ++k) lds[k][tid] += add[k];
-        __syncthreads();
-    }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        total[k] = lds[k][kNaSetupThreads - 1];
-        v[k] = lds[k][tid] - v[k];
+        T before = 0, all = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            const T s = lds[k][w];
+            before += (uint32_t)w < wave ? s : T(0);
+            all += s;
+        }
+        total[k] = all;
+        v[k] = before + incl[k] - v[k];
     }
     __syncthreads();
 }
 
-// Bucket of a shorter item of t tiles (t < tiles per item).
-__device__ __forceinline__ int na_bucket(uint32_t t) { return (int)min(bit_length(t), (uint32_t)(kNaBuckets - 1)); }
-
-// Items of one array for tiles per item P: cnt[kNaBuckets] whole items,
-// and one in the bucket of the rest (or of its head/tail bytes alone).
-__device__ __forceinline__ void na_count_items(const ArrayInfo &ai, uint32_t P, uint32_t (&cnt)[kNaBuckets + 1]) {
-    const bool edges = ai.edge0_len + ai.edge1_len > 0u;
-    const uint32_t rest = ai.n_tiles % P;
-    cnt[kNaBuckets] += ai.n_tiles / P;
-    if (rest != 0u || (ai.n_tiles == 0u && edges)) ++cnt[na_bucket(rest)];
+// 0..3 tiles: buckets 0..3; above, two buckets per bit length L >= 3, split
+// by the bit below the top one (4-5, 6-7, 8-11, 12-15, ...), so that
+// bucket order is within a factor 1.5 of size order.
+__device__ __forceinline__ int na_bucket(uint32_t t) {
+    if (t < 4u) return (int)t;
+    const uint32_t L = bit_length(t);
+    return (int)min(4u + 2u * (L - 3u) + ((t >> (L - 2u)) & 1u), (uint32_t)(kNaBuckets - 1));
 }
 
-// ---- setup steps (each kernel below is a composition of them) -----------
+// log2 of the smallest item size in bucket b < kNaBuckets, rounded down.
+__device__ __forceinline__ uint32_t na_bucket_lg_min(int b) {
+    return b < 4 ? (b >= 2 ? 1u : 0u) : (uint32_t)(b - 4) / 2u + 2u;
+}
+
+// Slots of one array's items within its setup block's share of the table:
+// its whole items take `whole` consecutive slots of the block's whole items
+// from f_whole on, its shorter item (if any; b >= 0) slot f_rest of the
+// block's bucket b.  The slots are claimed with atomics on the block's
+// per-bucket counters in LDS, so their order within a block and bucket is
+// arbitrary (counts do not depend on the order of items).
+struct NaSlots {
+    uint32_t whole, f_whole;
+    int b;
+    uint32_t f_rest;
+};
+
+__device__ __forceinline__ NaSlots na_claim(const ArrayInfo &ai, uint32_t P, uint32_t *bucket_cnt) {
+    const bool edges = ai.edge0_len + ai.edge1_len > 0u;
+    const uint32_t rest = ai.n_tiles % P;
+    NaSlots sl{ai.n_tiles / P, 0u, -1, 0u};
+    if (sl.whole != 0u) sl.f_whole = atomicAdd(&bucket_cnt[kNaBuckets], sl.whole);
+    if (rest != 0u || (ai.n_tiles == 0u && edges)) {
+        sl.b = na_bucket(rest);
+        sl.f_rest = atomicAdd(&bucket_cnt[sl.b], 1u);
+    }
+    return sl;
+}
 
 // Thread i <-> array i: validates descriptor i and writes its table entry
 // (an invalid one gets an empty entry).  Returns the entry; *bad and *tiles
@@ -204,56 +243,59 @@ __device__ __forceinline__ uint32_t na_layout(const uint32_t (&tot)[kNaBuckets +
     return next;
 }
 
-// Writes array i's items at base[k] + at[k] (k: whole items or the rest's
-// bucket); the array's first item carries its head/tail bytes.
-__device__ __forceinline__ void na_write_items(const ArrayInfo &ai, uint32_t i, uint32_t P,
-                                               const uint32_t (&base)[kNaBuckets + 1],
-                                               const uint32_t (&at)[kNaBuckets + 1], WorkItem *items) {
+// Writes array i's items: its whole items from slot f_whole on, its
+// shorter item (if sl.b >= 0) at slot f_rest; the array's first item
+// carries its head/tail bytes.
+__device__ __forceinline__ void na_write_items(const ArrayInfo &ai, uint32_t i, uint32_t P, const NaSlots &sl,
+                                               uint32_t f_whole, uint32_t f_rest, WorkItem *items) {
     const uint32_t edges = ai.edge0_len + ai.edge1_len > 0u ? 1u : 0u;
-    const uint32_t whole = ai.n_tiles / P, rest = ai.n_tiles % P;
-    uint32_t f = base[kNaBuckets] + at[kNaBuckets];
-    for (uint32_t k = 0; k < whole; ++k) items[f++] = WorkItem{i, k * P, (k + 1u) * P, k == 0u ? edges : 0u};
-    if (rest != 0u || (ai.n_tiles == 0u && edges)) {
-        const int b = na_bucket(rest);
-        items[base[b] + at[b]] = WorkItem{i, whole * P, ai.n_tiles, whole == 0u ? edges : 0u};
-    }
+    for (uint32_t k = 0; k < sl.whole; ++k) items[f_whole + k] = WorkItem{i, k * P, (k + 1u) * P, k == 0u ? edges : 0u};
+    if (sl.b >= 0) items[f_rest] = WorkItem{i, sl.whole * P, ai.n_tiles, sl.whole == 0u ? edges : 0u};
 }
 
-// The header for the walk (one thread): segments with their group sizes,
-// ticket count, cursor reset; and the count of invalid descriptors.
-__device__ void na_write_header(NaHeader *h, const uint32_t (&tot)[kNaBuckets + 1],
-                                const uint32_t (&base)[kNaBuckets + 1], uint32_t n_items, const NaChoice &c,
-                                uint32_t n_bad, uint32_t n, uint32_t *n_invalid_out) {
+// The header for the walk, by the 64 lanes of a block's first wave: lane j
+// builds segment j (whole items for j = 0, then the buckets from the
+// largest down) from the item totals per bucket in LDS, with its group size,
+// and wave prefix sums give each segment's first item and first ticket.
+// If `base_out` is given, the first item of each bucket goes there (LDS).
+// Also reports invalid descriptors.
+__device__ void na_write_header(NaHeader *h, const uint32_t *tot, const NaChoice &c, uint32_t n_bad, uint32_t n,
+                                uint32_t *n_invalid_out, uint32_t *base_out) {
+    const uint32_t j = __lane_id();
+    const bool seg = j < (uint32_t)kNaSegments;
+    const int b = seg ? kNaBuckets - (int)j : 0;  // this lane's bucket (kNaBuckets: whole items)
+    const uint32_t count = seg && c.ok ? tot[b] : 0u;
+    const uint32_t incl = wave_inclusive_scan(count);
+    const uint32_t base = incl - count;
+    const uint32_t n_items = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+    if (seg && base_out) base_out[b] = base;
     // group sizes are powers of two (log2 below), so this needs no division
     // past the one for the cap
     const uint32_t nw = max(c.waves, 1u);
     const uint32_t cap = n_items / nw;
     const uint32_t lg_cap = cap == 0u ? 0u : bit_length(cap) - 1u;
     const uint32_t lg_target = bit_length(kNaGroupTiles) - 1u;
-    uint32_t tickets = 0;
-    for (int j = 0; j < kNaSegments; ++j) {
-        const int b = kNaBuckets - j;  // segment j: whole items (b = kNaBuckets), then bucket b
-        // log2 of the segment's smallest item size, rounded down (P is at
-        // least 4; bucket b >= 1 holds items of 2^(b-1) tiles or more)
-        const uint32_t lg_min = b == kNaBuckets ? bit_length(c.P) - 1u : (b == 0 ? 0u : (uint32_t)(b - 1));
-        uint32_t lg_g = min(lg_target > lg_min ? lg_target - lg_min : 0u, lg_cap);
-        const uint32_t count = c.ok ? tot[b] : 0u;
-        while (lg_g > 0u) {
-            const uint32_t k = (count + (1u << lg_g) - 1u) >> lg_g;
-            if (k <= nw || k >= 2u * nw) break;
-            --lg_g;
-        }
-        h->seg[j] = NaSegment{tickets, base[b], count, 1u << lg_g};
-        tickets += (count + (1u << lg_g) - 1u) >> lg_g;
+    // log2 of the segment's smallest item size, rounded down (P is at least 4)
+    const uint32_t lg_min = b == kNaBuckets ? bit_length(c.P) - 1u : na_bucket_lg_min(b);
+    uint32_t lg_g = min(lg_target > lg_min ? lg_target - lg_min : 0u, lg_cap);
+    while (lg_g > 0u) {
+        const uint32_t k = (count + (1u << lg_g) - 1u) >> lg_g;
+        if (k <= nw || k >= 2u * nw) break;
+        --lg_g;
     }
-    h->cursor = 0u;
-    h->n_items = c.ok ? n_items : 0u;
-    h->n_tickets = tickets;
-    h->tiles_per_item = c.P;
-    h->ok = c.ok ? 1u : 0u;
-    h->n_bad = n_bad;
-    h->waves = c.waves;
-    if (n_invalid_out) *n_invalid_out = c.ok ? 0u : (n_bad ? n_bad : n);
+    const uint32_t tickets = (count + (1u << lg_g) - 1u) >> lg_g;
+    const uint32_t t_incl = wave_inclusive_scan(tickets);
+    if (seg) h->seg[j] = NaSegment{t_incl - tickets, base, count, 1u << lg_g};
+    if (j == 0) {
+        h->cursor = 0u;
+        h->n_items = n_items;
+        h->n_tickets = (uint32_t)__builtin_amdgcn_readlane((int)t_incl, kWave - 1);
+        h->tiles_per_item = c.P;
+        h->ok = c.ok ? 1u : 0u;
+        h->n_bad = n_bad;
+        h->waves = c.waves;
+        if (n_invalid_out) *n_invalid_out = c.ok ? 0u : (n_bad ? n_bad : n);
+    }
 }
 
 // ---- setup kernels ---------------------------------------------------------
@@ -267,23 +309,25 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_setup_one_block_kerne
     ArrayInfo *arrays = reinterpret_cast<ArrayInfo *>(scr + kNaArraysOff);
     WorkItem *items = reinterpret_cast<WorkItem *>(scr + kNaItemsOff);
     __shared__ uint64_t lds64[1][kNaSetupThreads];
-    __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupThreads];
+    __shared__ uint32_t lds32[1][kNaSetupThreads];
+    __shared__ uint32_t bucket_cnt[kNaBuckets + 1], lbase[kNaBuckets + 1];
     const uint32_t i = threadIdx.x;
+    if (i <= (uint32_t)kNaBuckets) bucket_cnt[i] = 0u;
     uint32_t bad[1];
     uint64_t tiles[1];
     const ArrayInfo ai = na_array_entry(descs, n, i, arrays, bad[0], tiles[0]);
     uint32_t n_bad[1];
     uint64_t T[1];
-    block_exclusive_scan<uint32_t, 1>(bad, lds32, n_bad);
+    block_exclusive_scan<uint32_t, 1>(bad, lds32, n_bad);  // its barriers also order the zeroing
     block_exclusive_scan<uint64_t, 1>(tiles, lds64, T);
     const NaChoice c = na_choose(T[0], n_bad[0], n, cus);
-    uint32_t cnt[kNaBuckets + 1] = {0};
-    if (c.ok && i < n) na_count_items(ai, c.P, cnt);
-    uint32_t tot[kNaBuckets + 1], base[kNaBuckets + 1];
-    block_exclusive_scan<uint32_t, kNaBuckets + 1>(cnt, lds32, tot);
-    const uint32_t n_items = na_layout(tot, base);
-    if (c.ok && i < n) na_write_items(ai, i, c.P, base, cnt, items);
-    if (i == 0) na_write_header(h, tot, base, n_items, c, n_bad[0], n, n_invalid_out);
+    NaSlots sl{0u, 0u, -1, 0u};
+    if (c.ok && i < n) sl = na_claim(ai, c.P, bucket_cnt);
+    __syncthreads();
+    if (i < (uint32_t)kWave) na_write_header(h, bucket_cnt, c, n_bad[0], n, n_invalid_out, lbase);
+    __syncthreads();
+    if (c.ok && i < n)
+        na_write_items(ai, i, c.P, sl, lbase[kNaBuckets] + sl.f_whole, sl.b >= 0 ? lbase[sl.b] + sl.f_rest : 0u, items);
 }
 
 // Larger batches, three kernels.  Setup 1, thread i <-> array i: the array
@@ -316,8 +360,10 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_count_kernel(uint32_t
     const ArrayInfo *arrays = reinterpret_cast<const ArrayInfo *>(scr + kNaArraysOff);
     NaPartial *part = reinterpret_cast<NaPartial *>(scr + kNaPartOff);
     __shared__ uint64_t lds64[1][kNaSetupThreads];
-    __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupThreads];
+    __shared__ uint32_t lds32[1][kNaSetupThreads];
+    __shared__ uint32_t bucket_cnt[kNaBuckets + 1];
     const uint32_t tid = threadIdx.x, nb = gridDim.x;
+    if (tid <= (uint32_t)kNaBuckets) bucket_cnt[tid] = 0u;
     uint32_t bad[1] = {tid < nb ? part[tid].bad : 0u};
     uint64_t tiles[1] = {tid < nb ? part[tid].tiles : 0ull};
     uint32_t n_bad[1];
@@ -326,24 +372,21 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_count_kernel(uint32_t
     block_exclusive_scan<uint64_t, 1>(tiles, lds64, T);
     const NaChoice c = na_choose(T[0], n_bad[0], n, cus);
     const uint32_t i = blockIdx.x * kNaSetupThreads + tid;
-    uint32_t cnt[kNaBuckets + 1] = {0};
-    if (c.ok && i < n) na_count_items(arrays[i], c.P, cnt);
-    uint32_t tot[kNaBuckets + 1];
-    block_exclusive_scan<uint32_t, kNaBuckets + 1>(cnt, lds32, tot);
-    if (tid == 0) {
-        for (int k = 0; k <= kNaBuckets; ++k) part[blockIdx.x].cnt[k] = tot[k];
-        if (blockIdx.x == 0) {
-            h->tiles_per_item = c.P;
-            h->ok = c.ok ? 1u : 0u;
-            h->n_bad = n_bad[0];
-            h->waves = c.waves;
-        }
+    if (c.ok && i < n) (void)na_claim(arrays[i], c.P, bucket_cnt);
+    __syncthreads();
+    if (tid <= (uint32_t)kNaBuckets) part[blockIdx.x].cnt[tid] = bucket_cnt[tid];
+    if (blockIdx.x == 0 && tid == 0) {
+        h->tiles_per_item = c.P;
+        h->ok = c.ok ? 1u : 0u;
+        h->n_bad = n_bad[0];
+        h->waves = c.waves;
     }
 }
 
 // Setup 3: every block scans the blocks' item counts (the same layout in
-// every block; within each bucket, blocks in order and arrays in order),
-// then thread i writes array i's items.  Block 0 completes the header.
+// every block; within each bucket, blocks in order), then thread i claims
+// slots in its block's share again and writes array i's items.  Block 0
+// completes the header.
 __global__ __launch_bounds__(kNaSetupThreads) void noalloc_items_kernel(uint32_t n, uint32_t *n_invalid_out,
                                                                         uint8_t *scr) {
     NaHeader *h = reinterpret_cast<NaHeader *>(scr);
@@ -351,31 +394,32 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_items_kernel(uint32_t
     const NaPartial *part = reinterpret_cast<const NaPartial *>(scr + kNaPartOff);
     WorkItem *items = reinterpret_cast<WorkItem *>(scr + kNaItemsOff);
     __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupThreads];
-    __shared__ uint32_t blk_base[kNaBuckets + 1];
+    __shared__ uint32_t bucket_cnt[kNaBuckets + 1], start[kNaBuckets + 1], ltot[kNaBuckets + 1];
     const uint32_t tid = threadIdx.x, nb = gridDim.x;
     const NaChoice c{h->waves, h->tiles_per_item, h->ok != 0u};
     const uint32_t n_bad = h->n_bad;
+    if (tid <= (uint32_t)kNaBuckets) bucket_cnt[tid] = 0u;
 
     uint32_t blk[kNaBuckets + 1], tot[kNaBuckets + 1], base[kNaBuckets + 1];
 #pragma unroll
     for (int k = 0; k <= kNaBuckets; ++k) blk[k] = tid < nb ? part[tid].cnt[k] : 0u;
     block_exclusive_scan<uint32_t, kNaBuckets + 1>(blk, lds32, tot);
-    if (tid == blockIdx.x)
-        for (int k = 0; k <= kNaBuckets; ++k) blk_base[k] = blk[k];
-    const uint32_t n_items = na_layout(tot, base);
-
-    const uint32_t i = blockIdx.x * kNaSetupThreads + tid;
-    uint32_t cnt[kNaBuckets + 1] = {0};
-    if (c.ok && i < n) na_count_items(arrays[i], c.P, cnt);
-    uint32_t unused[kNaBuckets + 1];
-    block_exclusive_scan<uint32_t, kNaBuckets + 1>(cnt, lds32, unused);  // also orders blk_base
-    if (c.ok && i < n) {
-        uint32_t at[kNaBuckets + 1];
+    (void)na_layout(tot, base);
+    if (tid == blockIdx.x)  // this block's share of each bucket starts here
 #pragma unroll
-        for (int k = 0; k <= kNaBuckets; ++k) at[k] = blk_base[k] + cnt[k];
-        na_write_items(arrays[i], i, c.P, base, at, items);
+        for (int k = 0; k <= kNaBuckets; ++k) start[k] = base[k] + blk[k];
+    if (tid == 0)
+#pragma unroll
+        for (int k = 0; k <= kNaBuckets; ++k) ltot[k] = tot[k];
+    __syncthreads();
+    const uint32_t i = blockIdx.x * kNaSetupThreads + tid;
+    if (c.ok && i < n) {
+        const ArrayInfo ai = arrays[i];
+        const NaSlots sl = na_claim(ai, c.P, bucket_cnt);
+        na_write_items(ai, i, c.P, sl, start[kNaBuckets] + sl.f_whole, sl.b >= 0 ? start[sl.b] + sl.f_rest : 0u,
+                       items);
     }
-    if (blockIdx.x == 0 && tid == 0) na_write_header(h, tot, base, n_items, c, n_bad, n, n_invalid_out);
+    if (blockIdx.x == 0 && tid < (uint32_t)kWave) na_write_header(h, ltot, c, n_bad, n, n_invalid_out, nullptr);
 }
 
 // Persistent walk: of the launched waves, the first `waves` (from the
@@ -396,25 +440,18 @@ __global__ __launch_bounds__(WPB *kWave) void noalloc_batched_kernel(uint8_t *sc
     uint32_t t = blockIdx.x * WPB + wave_in_block();
     if (t >= nw) return;
     // the segment table, read once (the loop's atomics would otherwise make
-    // the compiler reload it for every ticket)
-    uint32_t s_t0[kNaSegments], s_i0[kNaSegments], s_end[kNaSegments], s_g[kNaSegments];
-#pragma unroll
-    for (int j = 0; j < kNaSegments; ++j) {
-        s_t0[j] = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->seg[j].ticket0);
-        s_i0[j] = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->seg[j].item0);
-        s_end[j] = s_i0[j] + (uint32_t)__builtin_amdgcn_readfirstlane((int)h->seg[j].count);
-        s_g[j] = (uint32_t)__builtin_amdgcn_readfirstlane((int)h->seg[j].group);
-    }
+    // the compiler reload it for every ticket): lane j holds segment j
+    const uint32_t lane = __lane_id();
+    NaSegment sg{0xffffffffu, 0u, 0u, 1u};
+    if (lane < (uint32_t)kNaSegments) sg = h->seg[lane];
     while (t < n_tickets) {
-        uint32_t tk0 = 0, it0 = 0, end = 0, g = 1;
-#pragma unroll
-        for (int j = 0; j < kNaSegments; ++j) {
-            const bool in = t >= s_t0[j];
-            tk0 = in ? s_t0[j] : tk0;
-            it0 = in ? s_i0[j] : it0;
-            end = in ? s_end[j] : end;
-            g = in ? s_g[j] : g;
-        }
+        // the last segment whose first ticket is at most t (segment 0 starts at 0)
+        const uint64_t m = __ballot(sg.ticket0 <= t);
+        const int j = 63 - __builtin_clzll(m);
+        const uint32_t tk0 = (uint32_t)__builtin_amdgcn_readlane((int)sg.ticket0, j);
+        const uint32_t it0 = (uint32_t)__builtin_amdgcn_readlane((int)sg.item0, j);
+        const uint32_t end = it0 + (uint32_t)__builtin_amdgcn_readlane((int)sg.count, j);
+        const uint32_t g = (uint32_t)__builtin_amdgcn_readlane((int)sg.group, j);
         const uint32_t i0 = it0 + (t - tk0) * g;
         const uint32_t i1 = min(i0 + g, end);
         for (uint32_t i = i0; i < i1; ++i) run_item(arrays, items[i]);
