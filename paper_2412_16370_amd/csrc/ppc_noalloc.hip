@@ -7,9 +7,10 @@
 // counters), but the descriptor table is the caller's, in device memory, and
 // every table the kernels need lives in one file-scope device array,
 // `scratch`, of fixed size:
-//   [0, 256)                      header: work cursor, item counts, item size
-//   [256, 256 + 64 * 2^16)        one ArrayInfo per array (at most 2^16)
-//   [.., + 64 * 256)              per-block partial sums of the setup kernels
+//   [0, 512)                      header: work cursor, walk grid, item size,
+//                                 the item table's segments
+//   [512, 512 + 64 * 2^16)        one ArrayInfo per array (at most 2^16)
+//   [.., + 128 * 256)             per-block partial sums of the setup kernels
 //   [.., + 16 * 2^18)             work items (at most 2^18), largest first
 // Setup on the device, one thread per array: for at most 256 arrays one
 // kernel, else three (array table and block sums; walk grid, item size and
@@ -62,6 +63,7 @@ constexpr int kNaBuckets = 16;
 constexpr int kNaSegments = kNaBuckets + 1;  // [0]: whole items, [1 + (kNaBuckets - 1 - b)]: bucket b
 constexpr uint32_t kNaGroupTiles = 32;
 constexpr int kNaSetupThreads = 256;
+constexpr int kNaSetupWaves = kNaSetupThreads / kWave;
 constexpr uint32_t kNaMaxBlocks = kNaMaxArrays / kNaSetupThreads;
 static_assert(kNaMaxBlocks <= (uint32_t)kNaSetupThreads, "one thread per setup block in the block scans");
 constexpr int kNaWpb = 4;
@@ -115,8 +117,8 @@ static __device__ __align__(256) uint8_t scratch[kNaScratchBytes];
 
 // Exclusive prefix sums over the block's threads of K values at once:
 // within each wave by lane shuffles (six steps, no barrier), then the four
-// wave totals through LDS (`lds` needs kNaSetupThreads / kWave entries per
-// value).  total[k] receives the sum of value k over the block.
+// wave totals through LDS.  total[k] receives the sum of value k over the
+// block.
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
     const uint32_t lane = __lane_id();
@@ -129,8 +131,8 @@ __device__ __forceinline__ T wave_inclusive_scan(T x) {
 }
 
 template <typename T, int K>
-__device__ __forceinline__ void block_exclusive_scan(T (&v)[K], T (*lds)[kNaSetupThreads], T (&total)[K]) {
-    constexpr int kWaves = kNaSetupThreads / kWave;
+__device__ __forceinline__ void block_exclusive_scan(T (&v)[K], T (*lds)[kNaSetupWaves], T (&total)[K]) {
+    constexpr int kWaves = kNaSetupWaves;
     const uint32_t lane = __lane_id(), wave = threadIdx.x / kWave;
     T incl[K];
 #pragma unroll
@@ -308,8 +310,8 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_setup_one_block_kerne
     NaHeader *h = reinterpret_cast<NaHeader *>(scr);
     ArrayInfo *arrays = reinterpret_cast<ArrayInfo *>(scr + kNaArraysOff);
     WorkItem *items = reinterpret_cast<WorkItem *>(scr + kNaItemsOff);
-    __shared__ uint64_t lds64[1][kNaSetupThreads];
-    __shared__ uint32_t lds32[1][kNaSetupThreads];
+    __shared__ uint64_t lds64[1][kNaSetupWaves];
+    __shared__ uint32_t lds32[1][kNaSetupWaves];
     __shared__ uint32_t bucket_cnt[kNaBuckets + 1], lbase[kNaBuckets + 1];
     const uint32_t i = threadIdx.x;
     if (i <= (uint32_t)kNaBuckets) bucket_cnt[i] = 0u;
@@ -336,8 +338,8 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_arrays_kernel(const p
                                                                          uint32_t n, uint8_t *scr) {
     ArrayInfo *arrays = reinterpret_cast<ArrayInfo *>(scr + kNaArraysOff);
     NaPartial *part = reinterpret_cast<NaPartial *>(scr + kNaPartOff);
-    __shared__ uint64_t lds64[1][kNaSetupThreads];
-    __shared__ uint32_t lds32[1][kNaSetupThreads];
+    __shared__ uint64_t lds64[1][kNaSetupWaves];
+    __shared__ uint32_t lds32[1][kNaSetupWaves];
     uint32_t bad[1];
     uint64_t tiles[1];
     (void)na_array_entry(descs, n, blockIdx.x * kNaSetupThreads + threadIdx.x, arrays, bad[0], tiles[0]);
@@ -359,8 +361,8 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_count_kernel(uint32_t
     NaHeader *h = reinterpret_cast<NaHeader *>(scr);
     const ArrayInfo *arrays = reinterpret_cast<const ArrayInfo *>(scr + kNaArraysOff);
     NaPartial *part = reinterpret_cast<NaPartial *>(scr + kNaPartOff);
-    __shared__ uint64_t lds64[1][kNaSetupThreads];
-    __shared__ uint32_t lds32[1][kNaSetupThreads];
+    __shared__ uint64_t lds64[1][kNaSetupWaves];
+    __shared__ uint32_t lds32[1][kNaSetupWaves];
     __shared__ uint32_t bucket_cnt[kNaBuckets + 1];
     const uint32_t tid = threadIdx.x, nb = gridDim.x;
     if (tid <= (uint32_t)kNaBuckets) bucket_cnt[tid] = 0u;
@@ -393,7 +395,7 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_items_kernel(uint32_t
     const ArrayInfo *arrays = reinterpret_cast<const ArrayInfo *>(scr + kNaArraysOff);
     const NaPartial *part = reinterpret_cast<const NaPartial *>(scr + kNaPartOff);
     WorkItem *items = reinterpret_cast<WorkItem *>(scr + kNaItemsOff);
-    __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupThreads];
+    __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupWaves];
     __shared__ uint32_t bucket_cnt[kNaBuckets + 1], start[kNaBuckets + 1], ltot[kNaBuckets + 1];
     const uint32_t tid = threadIdx.x, nb = gridDim.x;
     const NaChoice c{h->waves, h->tiles_per_item, h->ok != 0u};
