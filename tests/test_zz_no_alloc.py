@@ -88,8 +88,8 @@ def check_against_oracle(got, pool, spec):
 
 
 def test_two_calls_in_a_row_match_the_plan_and_the_oracle(ppc):
-    # first call: 2,500 arrays up to 8 MiB (whole 1 MiB items and shorter
-    # ones), unaligned starts; second call: 400 arrays up to 64 KiB
+    # first call: 2,500 arrays up to 8 MiB (whole items and shorter ones),
+    # unaligned starts; second call: 400 arrays up to 64 KiB
     spec1 = synth.batch_spec(2500, seed=40, lo=16, hi=8 * MiB, start_jitter=64)
     spec2 = synth.batch_spec(400, seed=41, lo=16, hi=64 * 1024, start_jitter=64)
     pool1, pool2 = make_pool(spec1, seed=40), make_pool(spec2, seed=41)
