@@ -179,6 +179,41 @@ def test_one_block_and_grid_setup_boundary(ppc):
         check_against_oracle(got, pool, spec)
 
 
+def test_arrays_beyond_4GiB(ppc):
+    """Maximum sizes: a 5 GiB + 13-byte array (over 2^18 tiles of 16 KiB)
+    from an unaligned start and a 1 GiB array, next to small ragged arrays,
+    in one call; then the same descriptors again, so every count doubles.
+    Every array must match the oracle exactly."""
+    big, mid = (5 << 30) + 13, 1 << 30
+    small = [1, 15, 17, 4095, 16 * 1024 + 3, MiB + 77]
+    lengths = [big, mid] + small
+    widths = [32, 64, 8, 16, 32, 64, 8, 16]
+    starts, pos = [], 3  # the first array starts 3 bytes past a 16-byte boundary
+    for n in lengths:
+        starts.append(pos)
+        pos += n + 29
+    buf = synth.device_bernoulli(pos + 64, 0.5, seed=24, device=dev())
+    n = len(lengths)
+    counts = torch.zeros((n, 64), dtype=torch.int64, device=dev())
+    base, cbase = buf.data_ptr(), counts.data_ptr()
+    descs_dev = to_device(ppc, ppc.make_descs([base + s for s in starts], lengths,
+                                              [cbase + i * 512 for i in range(n)], widths))
+    bad = torch.full((1,), 12345, dtype=torch.int32, device=dev())
+    print("noalloc call: %d arrays, %d bytes" % (n, sum(lengths)), flush=True)
+    ppc.ppc_batch_noalloc(descs_dev, n, bad)
+    ppc.ppc_batch_noalloc(descs_dev, n, bad)
+    torch.cuda.synchronize()
+    assert int(bad.item()) == 0
+    got = ppc.counts_to_numpy(counts)
+    host = buf.cpu().numpy()
+    del buf
+    torch.cuda.empty_cache()
+    for i, (s, ln, w) in enumerate(zip(starts, lengths, widths)):
+        want = oracle.pospopcnt_mt(host[s:s + ln], w, 16)
+        assert np.array_equal(got[i, :w], want * np.uint64(2)), (i, ln, w)
+        assert not got[i, w:].any()
+
+
 def random_batch(rng, kind, n_tiles=(0, 0)):
     """A seeded batch of one of three shapes: 'mix' (1-700 arrays, lengths
     log-uniform up to 2 MiB, some empty), 'tiles' (n arrays of k whole tiles
