@@ -34,14 +34,10 @@
 
 namespace ppc {
 
-// Runs before every persistent launch: resets the work cursor and, for the
-// server, clears the batch's counters (a kernel, not a memset, so the whole
-// sequence can live in a hipGraph).
-__global__ void prologue_kernel(uint32_t *cursor, unsigned long long *clear, uint64_t n_clear) {
+// Resets the work cursor before a persistent launch that uses it (a
+// kernel, not a memset, so the sequence can live in a hipGraph).
+__global__ void prologue_kernel(uint32_t *cursor) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *cursor = 0u;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_clear;
-         i += (uint64_t)gridDim.x * blockDim.x)
-        clear[i] = 0ull;
 }
 
 // The persistent loop of one wave (index gw of nw): group gw first, then
@@ -180,14 +176,16 @@ std::vector<uint32_t> build_groups(const std::vector<WorkItem> &items, uint32_t 
 }
 
 hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, const uint32_t *groups_dev,
-                          uint32_t n_groups, uint32_t *cursor_dev, uint32_t waves, hipStream_t st,
-                          unsigned long long *clear, uint64_t n_clear) {
-    const uint64_t pblocks = std::max<uint64_t>(1, std::min<uint64_t>((n_clear + 255) / 256, 256));
-    hipLaunchKernelGGL(prologue_kernel, dim3((unsigned)pblocks), dim3(256), 0, st, cursor_dev, clear, n_clear);
-    if (n_groups == 0) return hipGetLastError();
+                          uint32_t n_groups, uint32_t *cursor_dev, uint32_t waves, hipStream_t st) {
     constexpr int kWpb = 4;
     const uint32_t w = std::max<uint32_t>(kWpb, std::min<uint32_t>(waves, n_groups + kWpb - 1));
     const uint32_t blocks = (w + kWpb - 1) / kWpb;
+    // the grid's waves are blocks * kWpb (run_groups' nw): with no more groups
+    // than that, no wave reads the cursor and the reset is left out (an
+    // empty batch keeps it, so that a captured graph is never empty)
+    if (n_groups == 0 || n_groups > blocks * (uint32_t)kWpb)
+        hipLaunchKernelGGL(prologue_kernel, dim3(1), dim3(64), 0, st, cursor_dev);
+    if (n_groups == 0) return hipGetLastError();
     hipLaunchKernelGGL(batched_kernel<kWpb>, dim3(blocks), dim3(kWpb * kWave), 0, st, arrays_dev, items_dev,
                        groups_dev, n_groups, cursor_dev);
     return hipGetLastError();

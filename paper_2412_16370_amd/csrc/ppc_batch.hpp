@@ -124,12 +124,12 @@ constexpr uint32_t kPlanGroupCost = 32;
 constexpr uint32_t kGroupMax = 64;
 std::vector<uint32_t> build_groups(const std::vector<WorkItem> &items, uint32_t waves, uint32_t cost);
 
-// Enqueues the prologue (cursor reset, and a clear of n_clear counters at
-// `clear` if given) and the persistent kernel on `st`.  Wave g of the grid
-// starts with group g; further groups come from the cursor.
+// Enqueues the persistent kernel on `st`, preceded by a cursor reset when
+// the cursor is used.  Wave g of the grid starts with group g; further
+// groups come from the cursor, which the kernel touches only when there
+// are more groups than the grid's waves.
 hipError_t launch_batched(const ArrayInfo *arrays_dev, const WorkItem *items_dev, const uint32_t *groups_dev,
-                          uint32_t n_groups, uint32_t *cursor_dev, uint32_t waves, hipStream_t st,
-                          unsigned long long *clear = nullptr, uint64_t n_clear = 0);
+                          uint32_t n_groups, uint32_t *cursor_dev, uint32_t waves, hipStream_t st);
 
 // Captures the fixed launch sequence of one server stream into a graph:
 // copy the batch tables (sizes read from the header) from pinned host
