@@ -172,7 +172,8 @@ typedef struct ppc_plan ppc_plan;
  * descriptors are copied; the buffers and counters they point to must stay
  * valid while the plan is used).  Validates every descriptor (PPC_EINVAL if
  * any is bad: same rules as the plain call), splits arrays into work items,
- * picks tiles per item and grid size (opts NULL = autotune + graph), uploads
+ * picks tiles per item and grid size (opts NULL: autotuned for batches of
+ * 64 MiB or more, a default setting below; runs replay a graph), uploads
  * the tables and captures the launch.  Autotuning times candidate settings
  * on `stream` with the counters redirected to scratch memory, so the
  * caller's counters are untouched; the choice is cached in the text file

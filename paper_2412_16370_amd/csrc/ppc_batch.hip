@@ -48,7 +48,9 @@ __global__ void prologue_kernel(uint32_t *cursor) {
 // for the whole of the current one, and near the end short groups then
 // wait behind long ones while other waves are idle (10,000-array mix, 4 MiB
 // items: a ~190 us tail, 6.6 against 6.9 TB/s).  The ticket's latency is
-// small against a group (at least 16 tiles).  If there are no more groups
+// small against a group, which closes at 16 or 32 tiles' worth of work
+// unless the batch is small enough to give every wave one group.  If there
+// are no more groups
 // than waves, a wave's first group is its only one and the cursor is not
 // touched: otherwise every wave's last atomic, which finds nothing, would
 // queue on the one address at the same moment.
