@@ -61,7 +61,7 @@ __device__ __forceinline__ void run_groups(const ArrayInfo *__restrict__ arrays,
     uint32_t grp = gw;
     while (grp < n_groups) {
         const uint32_t i0 = groups[grp], i1 = groups[grp + 1];
-        for (uint32_t i = i0; i < i1; ++i) run_item(arrays, items[i]);
+        run_items(arrays, items, i0, i1);
         if (n_groups <= nw) break;
         uint32_t ticket = 0;
         if (lane == 0) ticket = atomicAdd(cursor, 1u);

@@ -83,11 +83,11 @@ __host__ __device__ inline bool make_array_info(ArrayInfo &ai, const void *buf, 
     return true;
 }
 
-// One work item on one wave: the item's tiles (and the array's head/tail
-// bytes if flagged) are counted and folded into the array's counters.
-__device__ __forceinline__ void run_item(const ArrayInfo *__restrict__ arrays, const WorkItem &it) {
+// One work item on one wave, with its array's entry: the item's tiles (and
+// the array's head/tail bytes if flagged) are counted and folded into the
+// array's counters.
+__device__ __forceinline__ void run_item_of(const ArrayInfo &ai, const WorkItem &it) {
     const uint32_t lane = __lane_id();
-    const ArrayInfo ai = arrays[it.array];
     const bool has_edge = (it.flags & 1u) != 0u;
     uint4 edge = zero4();
     if (has_edge) {
@@ -100,6 +100,28 @@ __device__ __forceinline__ void run_item(const ArrayInfo *__restrict__ arrays, c
     const uint32_t acc =
         wave_count_tiles(ai.body, ai.n_chunks, ai.n_full, it.tile0, it.tile1, 1u, edge, has_edge);
     fold_add(acc, ai.width, ai.m, ai.counts);
+}
+
+// Items [i0, i1) one after another on one wave.  The next item's array
+// entry and the work item after it are loaded while the current item runs,
+// so a short item does not wait for its two descriptor loads (work item,
+// then array entry) after the previous one.
+__device__ __forceinline__ void run_items(const ArrayInfo *__restrict__ arrays, const WorkItem *__restrict__ items,
+                                          uint32_t i0, uint32_t i1) {
+    if (i0 >= i1) return;
+    const uint32_t last = i1 - 1u;
+    WorkItem it = items[i0];
+    ArrayInfo ai = arrays[it.array];
+    WorkItem nit = items[min(i0 + 1u, last)];
+    for (uint32_t i = i0; i < i1; ++i) {
+        // loads of valid entries only: past the last item they repeat it
+        const ArrayInfo nai = arrays[nit.array];
+        const WorkItem nnit = items[min(i + 2u, last)];
+        run_item_of(ai, it);
+        it = nit;
+        ai = nai;
+        nit = nnit;
+    }
 }
 
 // Appends the work items of array `idx` (tiles split into pieces of at most

@@ -456,7 +456,7 @@ __global__ __launch_bounds__(WPB *kWave) void noalloc_batched_kernel(uint8_t *sc
         const uint32_t g = (uint32_t)__builtin_amdgcn_readlane((int)sg.group, j);
         const uint32_t i0 = it0 + (t - tk0) * g;
         const uint32_t i1 = min(i0 + g, end);
-        for (uint32_t i = i0; i < i1; ++i) run_item(arrays, items[i]);
+        run_items(arrays, items, i0, i1);
         if (n_tickets <= nw) break;
         uint32_t ticket = 0;
         if (__lane_id() == 0u) ticket = atomicAdd(&h->cursor, 1u);
