@@ -114,6 +114,19 @@ __global__ void served_epilogue_kernel(const uint8_t *__restrict__ stage, unsign
     if (blockIdx.x == 0 && threadIdx.x == 0) *cursor = 0u;
 }
 
+hipError_t enqueue_served_batch(hipStream_t st, const uint8_t *stage_host, uint8_t *stage_dev, size_t items_off,
+                                size_t groups_off, unsigned long long *counts_dev, uint64_t *results_host,
+                                uint32_t *cursor_dev, uint32_t waves) {
+    constexpr int kWpb = 4;
+    hipLaunchKernelGGL(stage_copy_kernel, dim3(16), dim3(256), 0, st, stage_host, stage_dev, (uint32_t)items_off,
+                       (uint32_t)groups_off);
+    hipLaunchKernelGGL(served_batch_kernel<kWpb>, dim3((waves + kWpb - 1) / kWpb), dim3(kWpb * kWave), 0, st,
+                       (const uint8_t *)stage_dev, (uint32_t)items_off, (uint32_t)groups_off, cursor_dev);
+    hipLaunchKernelGGL(served_epilogue_kernel, dim3(64), dim3(256), 0, st, (const uint8_t *)stage_dev, counts_dev,
+                       results_host, cursor_dev);
+    return hipGetLastError();
+}
+
 hipError_t capture_served_graph(hipGraph_t *graph, hipGraphExec_t *exec, const uint8_t *stage_host,
                                 uint8_t *stage_dev, size_t items_off, size_t groups_off,
                                 unsigned long long *counts_dev, uint64_t *results_host, uint32_t *cursor_dev,
@@ -123,14 +136,8 @@ hipError_t capture_served_graph(hipGraph_t *graph, hipGraphExec_t *exec, const u
     if (e != hipSuccess) return e;
     e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        constexpr int kWpb = 4;
-        hipLaunchKernelGGL(stage_copy_kernel, dim3(16), dim3(256), 0, cap, stage_host, stage_dev, (uint32_t)items_off,
-                           (uint32_t)groups_off);
-        hipLaunchKernelGGL(served_batch_kernel<kWpb>, dim3((waves + kWpb - 1) / kWpb), dim3(kWpb * kWave), 0, cap,
-                           (const uint8_t *)stage_dev, (uint32_t)items_off, (uint32_t)groups_off, cursor_dev);
-        hipLaunchKernelGGL(served_epilogue_kernel, dim3(64), dim3(256), 0, cap, (const uint8_t *)stage_dev,
-                           counts_dev, results_host, cursor_dev);
-        const hipError_t launched = hipGetLastError();
+        const hipError_t launched = enqueue_served_batch(cap, stage_host, stage_dev, items_off, groups_off,
+                                                         counts_dev, results_host, cursor_dev, waves);
         e = hipStreamEndCapture(cap, graph);
         if (e == hipSuccess) e = launched;
     }

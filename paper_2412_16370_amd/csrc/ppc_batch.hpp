@@ -164,4 +164,9 @@ hipError_t capture_served_graph(hipGraph_t *graph, hipGraphExec_t *exec, const u
                                 unsigned long long *counts_dev, uint64_t *results_host, uint32_t *cursor_dev,
                                 uint32_t waves);
 
+// The same three kernels launched directly on `st` (no graph).
+hipError_t enqueue_served_batch(hipStream_t st, const uint8_t *stage_host, uint8_t *stage_dev, size_t items_off,
+                                size_t groups_off, unsigned long long *counts_dev, uint64_t *results_host,
+                                uint32_t *cursor_dev, uint32_t waves);
+
 }  // namespace ppc

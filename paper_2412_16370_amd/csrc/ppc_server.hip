@@ -192,7 +192,13 @@ void dispatch(ppc_server *s) {
         h->n_items = (uint32_t)items.size();
         h->n_groups = (uint32_t)groups.size() - 1u;
         l.t_launch = now_ns();
-        hipError_t e = hipGraphLaunch(l.exec, l.stream);
+        // with no other batch in flight the kernels go out directly, which
+        // costs the host less than a graph launch; under load the graph
+        bool others = false;
+        for (const auto &o : s->lanes) others = others || (&o != &l && o.busy);
+        hipError_t e = others ? hipGraphLaunch(l.exec, l.stream)
+                              : enqueue_served_batch(l.stream, l.stage_host, l.stage_dev, s->items_off, s->groups_off,
+                                                     l.counts_dev, l.results_host, l.cursor_dev, s->cfg.waves);
         if (e == hipSuccess) e = hipEventRecord(l.done, l.stream);
         if (e != hipSuccess) {
             l.failed = true;  // retire() reports the batch with status PPC_EDEVICE
