@@ -689,6 +689,24 @@ def main():
     log("density matrix (GB/s back to back): " + "; ".join(
         "p=%s: %s" % (p, " ".join("%s" % v[str(w)]["GBps"] for w in WIDTHS)) for p, v in density.items()))
 
+    # the total popcount (the same front end, all 64 positions summed into
+    # one counter) on the same buffers, back to back
+    total = torch.zeros(1, dtype=torch.int64, device=dev)
+    done_ms, n_pc = 0.0, 0
+    while done_ms < args.kernel_seconds * 1e3 or n_pc < 100:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in range(100):
+            lib.ppc_popcount(total.data_ptr(), bptr[i % 4], CALL_BYTES, sp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        done_ms += e0.elapsed_time(e1)
+        n_pc += 100
+    popcount = {"GBps": round(CALL_BYTES * n_pc / (done_ms * 1e-3) / 1e9, 1),
+                "us_per_launch": round(done_ms / n_pc * 1e3, 2), "launches": n_pc}
+    log("total popcount, back to back: %.2f us per 256 MiB launch -> %.1f GB/s"
+        % (popcount["us_per_launch"], popcount["GBps"]))
+
     def us_stats(v):
         v = sorted(v)
         return {"avg": round(sum(v) / len(v) * 1e3, 2), "median": round(v[len(v) // 2] * 1e3, 2),
@@ -760,6 +778,7 @@ def main():
                   % (args.kernel_seconds, steps_timed * len(WIDTHS) * CALL_BYTES / wall_timed / 1e9),
         "per_width_GBps": per_width,
         "per_width_b2b_GBps": per_width_b2b,
+        "popcount_256MiB_b2b": popcount,
         "density_GBps_b2b": density,
         "read_roofline_GBps": round(rl_gbps, 1),
         "read_roofline_b2b_GBps": round(rl_b2b_gbps, 1),
