@@ -301,6 +301,34 @@ __device__ __forceinline__ uint32_t planes_position_counts(const Planes &pl, uin
     return wave_position_counts(p, 4u + b_used);
 }
 
+// For the total popcount only: the lane's planes popcounted with their
+// weights, sum over e of 2^e * popcount(plane e) (the Harley-Seal total of
+// Section 3.3), with no cross-lane step.  The caller sums the lanes.  Planes
+// e >= e_used are zero and are skipped.
+__device__ __forceinline__ uint32_t lane_total(const uint4 (&p)[kPlanes], uint32_t e_used) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int e = 0; e < kPlanes; ++e) {
+        if ((uint32_t)e < e_used) {
+            const uint32_t c = (uint32_t)__builtin_popcount(p[e].x) + (uint32_t)__builtin_popcount(p[e].y) +
+                               (uint32_t)__builtin_popcount(p[e].z) + (uint32_t)__builtin_popcount(p[e].w);
+            t += c << e;
+        }
+    }
+    return t;
+}
+
+__device__ __forceinline__ uint32_t planes_lane_total(const Planes &pl, uint32_t b_used) {
+    uint4 p[kPlanes];
+    p[0] = pl.a1;
+    p[1] = pl.a2;
+    p[2] = pl.a4;
+    p[3] = pl.a8;
+#pragma unroll
+    for (int k = 0; k < kMaxK1; ++k) p[4 + k] = pl.b[k];
+    return lane_total(p, 4u + b_used);
+}
+
 // Streaming (non-temporal) 16-byte load: the input is read exactly once, so
 // it is marked as not worth keeping in the caches.
 __device__ __forceinline__ uint4 load_stream(const uint4 *p) {
@@ -335,6 +363,7 @@ __device__ __forceinline__ void load_tile(uint4 (&v)[kLoadsPerTile], const uint4
 // the current tile, so the compiler's wait counts let those loads stay in
 // flight (a conditional load there makes it wait for them).  The last one
 // or two whole tiles are peeled off after the loop.
+template <bool kTotal = false>
 __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t n_chunks, uint32_t n_full,
                                                      uint32_t t0, uint32_t t_end, uint32_t stride, uint4 edge,
                                                      bool has_edge) {
@@ -361,7 +390,7 @@ __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t
             for (int e = 0; e < kPlanes; ++e) p[e] = zero4();
             p[0] = make_uint4(v.x ^ edge.x, v.y ^ edge.y, v.z ^ edge.z, v.w ^ edge.w);
             p[1] = make_uint4(v.x & edge.x, v.y & edge.y, v.z & edge.z, v.w & edge.w);
-            return wave_position_counts(p, 2u);
+            return kTotal ? lane_total(p, 2u) : wave_position_counts(p, 2u);
         }
         // A partial tile alone, of k <= kFewChunks chunks per lane: with the
         // edge chunk a bit sees at most 15 inputs, so the carry-save network
@@ -389,7 +418,8 @@ __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t
             p[3] = pl.a8;
 #pragma unroll
             for (int e = 4; e < kPlanes; ++e) p[e] = zero4();
-            return wave_position_counts(p, bit_length(k + (has_edge ? 1u : 0u)));
+            const uint32_t e_used = bit_length(k + (has_edge ? 1u : 0u));
+            return kTotal ? lane_total(p, e_used) : wave_position_counts(p, e_used);
         }
     }
     Planes pl;
@@ -417,7 +447,7 @@ __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t
             add_tile(vb);
             i += 2u;
             if (seg >= kFlushAt) {
-                acc += planes_position_counts(pl, kMaxK1);
+                acc += kTotal ? planes_lane_total(pl, kMaxK1) : planes_position_counts(pl, kMaxK1);
                 pl.clear();
                 seg = 0;
             }
@@ -443,7 +473,7 @@ __device__ __forceinline__ uint32_t wave_count_tiles(const uint4 *body, uint64_t
         add_tile(v);
         any = true;
     }
-    if (any) acc += planes_position_counts(pl, bit_length(seg));
+    if (any) acc += kTotal ? planes_lane_total(pl, bit_length(seg)) : planes_position_counts(pl, bit_length(seg));
     return acc;
 }
 

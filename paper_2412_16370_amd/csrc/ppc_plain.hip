@@ -50,7 +50,9 @@ struct PlainArgs {
 // the grid), so one load instruction of a wave reads 1 KiB and the 16 loads
 // of a tile 16 KiB, all contiguous; at any moment the grid works on one
 // contiguous window.
-template <int WPB>
+// kTotal: the total popcount (width 0); each lane returns its share of the
+// total rather than a position's count, and the fold sums the lanes.
+template <int WPB, bool kTotal = false>
 __global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wib = wave_in_block();
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
         }
     }
     const uint32_t acc =
-        wave_count_tiles(a.body, a.n_chunks, a.n_full_tiles, gw, a.n_tiles, nw, edge, gw == 0);
+        wave_count_tiles<kTotal>(a.body, a.n_chunks, a.n_full_tiles, gw, a.n_tiles, nw, edge, gw == 0);
 
     __shared__ uint32_t part[WPB][kWave];
     part[wib][lane] = acc;
@@ -151,6 +153,15 @@ struct LaunchEvents {
 };
 
 static hipError_t launch_plain(const PlainArgs &a, unsigned blocks, unsigned wpb, hipStream_t st, LaunchEvents ev) {
+    if (a.width == 0u) {
+        if (wpb == 2)
+            hipExtLaunchKernelGGL((pospop_plain_kernel<2, true>), dim3(blocks), dim3(128), 0, st, ev.start, ev.stop, 0, a);
+        else if (wpb == 4)
+            hipExtLaunchKernelGGL((pospop_plain_kernel<4, true>), dim3(blocks), dim3(256), 0, st, ev.start, ev.stop, 0, a);
+        else
+            hipExtLaunchKernelGGL((pospop_plain_kernel<8, true>), dim3(blocks), dim3(512), 0, st, ev.start, ev.stop, 0, a);
+        return hipGetLastError();
+    }
     if (wpb == 2)
         hipExtLaunchKernelGGL((pospop_plain_kernel<2>), dim3(blocks), dim3(128), 0, st, ev.start, ev.stop, 0, a);
     else if (wpb == 4)

@@ -153,6 +153,21 @@ def test_small_grids_force_many_segments(geometry, waves, wpb):
         assert np.array_equal(got, oracle.pospopcnt_mt(host[off:], w, HOST_THREADS))
 
 
+@pytest.mark.parametrize("waves,wpb", [(1, 2), (8, 8), (64, 4)])
+def test_total_popcount_on_small_grids(geometry, waves, wpb):
+    """The total popcount with each wave walking hundreds of tiles (several
+    segment flushes of its per-lane totals), aligned and unaligned starts."""
+    ppc = geometry
+    ppc.ppc_set_plain_geometry(waves, wpb)
+    host = synth.random_bytes((32 << 20) + 77, seed=100 + waves)
+    buf = torch.from_numpy(host).to(dev())
+    for off in (0, 9):
+        total = torch.zeros(1, dtype=torch.int64, device=dev())
+        ppc.ppc_popcount(total, buf[off:])
+        torch.cuda.synchronize()
+        assert int(ppc.counts_to_numpy(total)[0]) == int(np.unpackbits(host[off:]).sum()), (waves, wpb, off)
+
+
 def test_just_over_4GiB_ragged(geometry):
     n = (4 << 30) + 4099
     buf = synth.device_bernoulli(n, 0.5, seed=7, device=dev())
