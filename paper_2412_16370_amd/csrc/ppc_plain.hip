@@ -68,7 +68,7 @@ __global__ __launch_bounds__(WPB *kWave) void pospop_plain_kernel(PlainArgs a) {
         }
     }
     const uint32_t acc =
-        wave_count_tiles<kTotal>(a.body, a.n_chunks, a.n_full_tiles, gw, a.n_tiles, nw, edge, gw == 0);
+        wave_count_tiles<kTotal, true>(a.body, a.n_chunks, a.n_full_tiles, gw, a.n_tiles, nw, edge, gw == 0);
 
     __shared__ uint32_t part[WPB][kWave];
     part[wib][lane] = acc;
