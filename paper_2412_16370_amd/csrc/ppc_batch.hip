@@ -77,6 +77,45 @@ __global__ __launch_bounds__(WPB *kWave) void batched_kernel(const ArrayInfo *__
     run_groups(arrays, items, groups, n_groups, cursor, blockIdx.x * WPB + wave_in_block(), gridDim.x * WPB);
 }
 
+// Small arrays (see is_small_array): wave g of nw takes entries g, g + nw,
+// ... of the index table, loading the next entry's descriptor while the
+// current array runs.  WPE waves per SIMD: 8 for at most two chunks per
+// lane (63-64 VGPRs), 4 above (69-108 VGPRs).
+template <int K, int WPE>
+__global__ __launch_bounds__(kSmallWpb *kWave) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void
+small_arrays_kernel(const ArrayInfo *__restrict__ arrays, const uint32_t *__restrict__ idx, uint32_t n) {
+    const uint32_t nw = gridDim.x * kSmallWpb;
+    uint32_t i = blockIdx.x * kSmallWpb + wave_in_block();
+    if (i >= n) return;
+    ArrayInfo ai = arrays[idx[i]];
+    for (; i < n; i += nw) {
+        const ArrayInfo nai = arrays[idx[min(i + nw, n - 1u)]];  // the last entry again past the end
+        run_small_array<K>(ai);
+        ai = nai;
+    }
+}
+
+hipError_t launch_small_arrays(const ArrayInfo *arrays_dev, const uint32_t *idx_dev, uint32_t n, uint32_t k_max,
+                               int cus, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const uint32_t k = small_k_class(k_max);
+    const uint32_t wpe = k <= 2u ? 8u : 4u;
+    // one round of resident blocks at most: 4 SIMDs x wpe waves per CU
+    const uint32_t blocks =
+        std::max<uint32_t>(1u, std::min<uint32_t>((uint32_t)std::max(cus, 1) * wpe, (n + kSmallWpb - 1) / kSmallWpb));
+    const dim3 grid(blocks), block(kSmallWpb * kWave);
+    switch (k) {
+    case 1: hipLaunchKernelGGL((small_arrays_kernel<1, 8>), grid, block, 0, st, arrays_dev, idx_dev, n); break;
+    case 2: hipLaunchKernelGGL((small_arrays_kernel<2, 8>), grid, block, 0, st, arrays_dev, idx_dev, n); break;
+    case 4: hipLaunchKernelGGL((small_arrays_kernel<4, 4>), grid, block, 0, st, arrays_dev, idx_dev, n); break;
+    case 8: hipLaunchKernelGGL((small_arrays_kernel<8, 4>), grid, block, 0, st, arrays_dev, idx_dev, n); break;
+    default:
+        hipLaunchKernelGGL((small_arrays_kernel<kSmallMaxK, 4>), grid, block, 0, st, arrays_dev, idx_dev, n);
+        break;
+    }
+    return hipGetLastError();
+}
+
 // ---- server batch sequence (captured once per stream) ---------------------
 __global__ void stage_copy_kernel(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, uint32_t items_off,
                                   uint32_t groups_off) {
@@ -258,7 +297,9 @@ struct ppc_plan {
     WorkItem *items_dev = nullptr;
     uint32_t *groups_dev = nullptr;
     uint32_t *cursor_dev = nullptr;
+    uint32_t *small_dev = nullptr;  // indices of the arrays run by the small-array kernel
     uint32_t n_items = 0, n_groups = 0;
+    uint32_t n_small = 0, small_k = 0;  // small arrays and their most chunks per lane
     uint32_t tiles_per_item = 0;
     uint32_t waves = 0;
     uint64_t total_bytes = 0;
@@ -278,15 +319,44 @@ void plan_free(ppc_plan *p) {
     if (p->items_dev) (void)hipFree(p->items_dev);
     if (p->groups_dev) (void)hipFree(p->groups_dev);
     if (p->cursor_dev) (void)hipFree(p->cursor_dev);
+    if (p->small_dev) (void)hipFree(p->small_dev);
     delete p;
 }
 
+// Work items of every array that the small-array kernel does not take.
 std::vector<WorkItem> build_items(const std::vector<ArrayInfo> &arrays, uint32_t tiles_per_item) {
     std::vector<WorkItem> items;
     items.reserve(arrays.size() * 2);
-    for (uint32_t i = 0; i < (uint32_t)arrays.size(); ++i) append_items(items, arrays[i], i, tiles_per_item);
+    for (uint32_t i = 0; i < (uint32_t)arrays.size(); ++i)
+        if (!is_small_array(arrays[i])) append_items(items, arrays[i], i, tiles_per_item);
     sort_items_lpt(items);
     return items;
+}
+
+// The small arrays with anything to count, in table order; k_max = their
+// most chunks per lane.
+std::vector<uint32_t> small_arrays(const std::vector<ArrayInfo> &arrays, uint32_t &k_max) {
+    std::vector<uint32_t> idx;
+    k_max = 0;
+    for (uint32_t i = 0; i < (uint32_t)arrays.size(); ++i) {
+        const ArrayInfo &a = arrays[i];
+        if (!is_small_array(a) || a.n_chunks + a.edge0_len + a.edge1_len == 0) continue;
+        idx.push_back(i);
+        k_max = std::max(k_max, small_chunks_per_lane(a));
+    }
+    return idx;
+}
+
+// One run of the plan on `st`: the persistent kernel over the work items
+// (or, for an empty plan, its cursor reset alone, so that a captured graph
+// is never empty), then the small-array kernel.
+hipError_t plan_enqueue(const ppc_plan *p, hipStream_t st) {
+    if (p->n_groups > 0 || p->n_small == 0) {
+        const hipError_t e =
+            launch_batched(p->arrays_dev, p->items_dev, p->groups_dev, p->n_groups, p->cursor_dev, p->waves, st);
+        if (e != hipSuccess) return e;
+    }
+    return launch_small_arrays(p->arrays_dev, p->small_dev, p->n_small, p->small_k, device_cus(p->device), st);
 }
 
 // Times one (tiles_per_item, waves) candidate on the plan's arrays with the
@@ -438,7 +508,9 @@ ppc_status ppc_plan_create(ppc_plan **out, const ppc_desc *descs, size_t n, cons
         const std::string key = tune_key(p);
         if (want_tune && tune_lookup(key, bp, bw)) {
             p->tuned = 2;
-        } else if (want_tune && n > 0 && p->total_bytes >= ((uint64_t)64 << 20)) {
+        } else if (want_tune && n > 0 && p->total_bytes >= ((uint64_t)64 << 20) &&
+                   std::any_of(p->arrays.begin(), p->arrays.end(),
+                               [](const ArrayInfo &a) { return !is_small_array(a); })) {
             ppc_status rc = autotune(p, st, bp, bw);
             if (rc != PPC_OK) {
                 plan_free(p);
@@ -454,10 +526,13 @@ ppc_status ppc_plan_create(ppc_plan **out, const ppc_desc *descs, size_t n, cons
     p->waves = wv;
     std::vector<WorkItem> items = build_items(p->arrays, p->tiles_per_item);
     std::vector<uint32_t> groups = build_groups(items, p->waves, kPlanGroupCost);
+    const std::vector<uint32_t> small = small_arrays(p->arrays, p->small_k);
     p->n_items = (uint32_t)items.size();
     p->n_groups = (uint32_t)groups.size() - 1u;
+    p->n_small = (uint32_t)small.size();
     if ((n > 0 && hipMalloc(&p->arrays_dev, n * sizeof(ArrayInfo)) != hipSuccess) ||
         (!items.empty() && hipMalloc(&p->items_dev, items.size() * sizeof(WorkItem)) != hipSuccess) ||
+        (!small.empty() && hipMalloc(&p->small_dev, small.size() * sizeof(uint32_t)) != hipSuccess) ||
         hipMalloc(&p->groups_dev, groups.size() * sizeof(uint32_t)) != hipSuccess) {
         plan_free(p);
         return PPC_ENOMEM;
@@ -465,6 +540,8 @@ ppc_status ppc_plan_create(ppc_plan **out, const ppc_desc *descs, size_t n, cons
     if ((n > 0 && hipMemcpyAsync(p->arrays_dev, p->arrays.data(), n * sizeof(ArrayInfo), hipMemcpyHostToDevice,
                                  st) != hipSuccess) ||
         (!items.empty() && hipMemcpyAsync(p->items_dev, items.data(), items.size() * sizeof(WorkItem),
+                                          hipMemcpyHostToDevice, st) != hipSuccess) ||
+        (!small.empty() && hipMemcpyAsync(p->small_dev, small.data(), small.size() * sizeof(uint32_t),
                                           hipMemcpyHostToDevice, st) != hipSuccess) ||
         hipMemcpyAsync(p->groups_dev, groups.data(), groups.size() * sizeof(uint32_t), hipMemcpyHostToDevice, st) !=
             hipSuccess ||
@@ -478,9 +555,7 @@ ppc_status ppc_plan_create(ppc_plan **out, const ppc_desc *descs, size_t n, cons
         bool ok = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
         if (ok) {
-            const bool launched =
-                launch_batched(p->arrays_dev, p->items_dev, p->groups_dev, p->n_groups, p->cursor_dev, p->waves, cap) ==
-                hipSuccess;
+            const bool launched = plan_enqueue(p, cap) == hipSuccess;
             ok = hipStreamEndCapture(cap, &p->graph) == hipSuccess && launched;
         }
         ok = ok && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
@@ -498,16 +573,13 @@ ppc_status ppc_plan_run(ppc_plan *p, void *stream) {
     if (!p) return PPC_EINVAL;
     hipStream_t st = (hipStream_t)stream;
     if (p->use_graph) return hipGraphLaunch(p->exec, st) == hipSuccess ? PPC_OK : PPC_EDEVICE;
-    return launch_batched(p->arrays_dev, p->items_dev, p->groups_dev, p->n_groups, p->cursor_dev, p->waves, st) ==
-                   hipSuccess
-               ? PPC_OK
-               : PPC_EDEVICE;
+    return plan_enqueue(p, st) == hipSuccess ? PPC_OK : PPC_EDEVICE;
 }
 
 ppc_status ppc_plan_get_info(const ppc_plan *p, ppc_plan_info *info) {
     if (!p || !info) return PPC_EINVAL;
     info->n_arrays = p->arrays.size();
-    info->n_items = p->n_items;
+    info->n_items = p->n_items + p->n_small;  // a small array is one item
     info->total_bytes = p->total_bytes;
     info->tiles_per_item = p->tiles_per_item;
     info->waves = p->waves;

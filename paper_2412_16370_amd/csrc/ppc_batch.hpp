@@ -124,6 +124,89 @@ __device__ __forceinline__ void run_items(const ArrayInfo *__restrict__ arrays, 
     }
 }
 
+// ---- arrays shorter than one tile: a kernel of their own -------------------
+// Such an array is a single work item on which a wave holds at most
+// kSmallMaxK chunks per lane, so the tile walk only ever takes one of its
+// two short paths.  Those need a fraction of the registers of the whole
+// walk (63-108 VGPRs against 223), so a kernel built for them alone runs
+// 4 or 8 waves per SIMD instead of 2: two to four times as many of these
+// short, latency-bound items keep their loads in flight.  Plans give such
+// arrays to this kernel.
+constexpr uint32_t kSmallMaxK = 14;
+constexpr int kSmallWpb = 4;
+
+__host__ __device__ inline bool is_small_array(const ArrayInfo &ai) {
+    return ai.n_full == 0 && ai.n_chunks <= (uint64_t)kSmallMaxK * kWave;
+}
+
+// Chunks per lane of a small array's body (0 if it has none).
+__host__ __device__ inline uint32_t small_chunks_per_lane(const ArrayInfo &ai) {
+    return (uint32_t)((ai.n_chunks + kWave - 1u) / kWave);
+}
+
+// The chunks-per-lane bound a small-array launch is built for: 1, 2, 4, 8
+// or kSmallMaxK.
+inline uint32_t small_k_class(uint32_t k) { return k <= 1u ? 1u : k <= 2u ? 2u : k <= 4u ? 4u : k <= 8u ? 8u : kSmallMaxK; }
+
+// The tile walk's two short paths for a small array (body of k <= K chunks
+// per lane, no whole tile): at most one chunk per lane goes with the edge
+// chunk through one half adder; more go through the carry-save network,
+// which leaves the count in binary in bit_length(k + 1) planes.  Returns
+// lane L = count at address position L.
+template <int K>
+__device__ __forceinline__ uint32_t wave_count_small(const uint4 *body, uint64_t n_chunks, uint4 edge,
+                                                     bool has_edge) {
+    const uint32_t lane = __lane_id();
+    uint4 p[kPlanes];
+#pragma unroll
+    for (int e = 0; e < kPlanes; ++e) p[e] = zero4();
+    if (n_chunks <= (uint64_t)kWave) {
+        uint4 v = zero4();
+        if (lane < n_chunks) v = body[lane];
+        p[0] = make_uint4(v.x ^ edge.x, v.y ^ edge.y, v.z ^ edge.z, v.w ^ edge.w);
+        p[1] = make_uint4(v.x & edge.x, v.y & edge.y, v.z & edge.z, v.w & edge.w);
+        return reduce_planes<4>(p);
+    }
+    const uint32_t k = (uint32_t)((n_chunks + kWave - 1u) / kWave);
+    uint4 v[kLoadsPerTile];
+#pragma unroll
+    for (int j = 0; j < kLoadsPerTile; ++j) {
+        const uint64_t idx = (uint64_t)j * kWave + lane;
+        v[j] = (j < K && idx < n_chunks) ? body[idx] : zero4();
+    }
+    Planes pl;
+    pl.a1 = edge;
+    pl.a2 = pl.a4 = pl.a8 = zero4();
+    (void)pl.csa16(v);
+    p[0] = pl.a1;
+    p[1] = pl.a2;
+    p[2] = pl.a4;
+    p[3] = pl.a8;
+    // k <= 14 and the edge chunk: at most 15 inputs per bit, four planes
+    return bit_length(k + (has_edge ? 1u : 0u)) <= 2u ? reduce_planes<4>(p) : reduce_planes<6>(p);
+}
+
+// One small array on one wave: its head/tail bytes and body are counted
+// and folded into its counters (what run_item_of does for its one item).
+template <int K>
+__device__ __forceinline__ void run_small_array(const ArrayInfo &ai) {
+    const uint32_t lane = __lane_id();
+    const bool has_edge = ai.edge0_len + ai.edge1_len > 0u;
+    uint4 edge = zero4();
+    if (lane < 32) {
+        if (lane < ai.edge0_len) edge = byte_as_chunk((uint64_t)(ai.edge0 + lane), ai.edge0[lane]);
+    } else if (lane - 32 < ai.edge1_len) {
+        edge = byte_as_chunk((uint64_t)(ai.edge1 + (lane - 32)), ai.edge1[lane - 32]);
+    }
+    const uint32_t acc = wave_count_small<K>(ai.body, ai.n_chunks, edge, has_edge);
+    fold_add(acc, ai.width, ai.m, ai.counts);
+}
+
+// Enqueues the small-array kernel over the `n` array indices at idx_dev,
+// every one a small array with at most k_max chunks per lane.
+hipError_t launch_small_arrays(const ArrayInfo *arrays_dev, const uint32_t *idx_dev, uint32_t n, uint32_t k_max,
+                               int cus, hipStream_t st);
+
 // Appends the work items of array `idx` (tiles split into pieces of at most
 // `tiles_per_item`).
 void append_items(std::vector<WorkItem> &items, const ArrayInfo &ai, uint32_t idx, uint32_t tiles_per_item);

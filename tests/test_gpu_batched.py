@@ -272,6 +272,54 @@ def test_partial_tiles_of_4_to_16_KiB(ppc, w):
         assert np.array_equal(ppc.counts_to_numpy(one), want[r]), "plain: start %d, length %d" % (starts[r], lens[r])
 
 
+@pytest.mark.parametrize("k_max", (1, 2, 3, 4, 6, 8, 11, 14, 15))
+def test_small_array_kernel_chunk_classes(ppc, k_max):
+    """Plans give arrays shorter than one tile, of at most 14 chunks per lane,
+    to a kernel of their own, built for 1, 2, 4, 8 or 14 chunks per lane by
+    the batch's longest such array.  A batch whose longest array holds
+    k_max * 1024 bytes (k_max chunks per lane from an aligned start; at 15 it
+    is no longer small), lengths from 0 up to that at every start residue
+    mod 16, arrays of a tile or more beside them and arrays that share
+    counter rows: after a graph replay, a second replay and a run without the
+    graph every row holds three times the oracle's counts."""
+    rng = np.random.default_rng(900 + k_max)
+    top, lo = k_max * 1024, 64
+    region = synth.random_bytes(top + 80 * 1024, seed=900 + k_max)
+    host = np.concatenate([np.full(lo, 0xFF, np.uint8), region, np.full(128, 0xFF, np.uint8)])
+    buf = torch.from_numpy(host).to(dev())
+    assert buf.data_ptr() % 16 == 0
+    fixed = [0, 1, 15, 16, 17, 31, 1023, 1024, 1025, top - 1, top, top + 15]
+    lens = fixed + [int(x) for x in rng.integers(0, top + 16, size=240)] + [16384, 20000, 65539]
+    offs = [0] * len(fixed) + [int(x) for x in rng.integers(0, 16, size=240)] + [0, 5, 9]
+    offs[len(fixed) - 1] = 7  # top + 15 bytes from an unaligned start as well
+    n = len(lens)
+    starts = [lo + o for o in offs]
+    widths = [int(x) for x in rng.choice(np.array([8, 16, 32, 64]), size=n)]
+    rows = list(range(n))
+    for a, b in ((3, n - 1), (7, 40), (41, 42)):  # shared counter rows
+        rows[b] = rows[a]
+    want = np.zeros((n, 64), dtype=np.uint64)
+    for i, r in enumerate(oracle.pospopcnt_ranges(host, starts, lens, widths)):
+        want[rows[i], :widths[i]] += r
+    counts = torch.zeros((n, 64), dtype=torch.int64, device=dev())
+    base, cbase = buf.data_ptr(), counts.data_ptr()
+    descs = ppc.make_descs([base + s for s in starts], lens, [cbase + r * 64 * 8 for r in rows], widths)
+    for graph in (1, 0):
+        plan = ppc.ppc_plan_create(descs, n, ppc.ppc_plan_opts(16, 0, 0, graph, 0))
+        try:
+            for _ in range(2 if graph else 1):
+                ppc.ppc_plan_run(plan)
+            torch.cuda.synchronize()
+            info = ppc.ppc_plan_get_info(plan)
+        finally:
+            ppc.ppc_plan_destroy(plan)
+        assert info["graph"] == graph
+    got = ppc.counts_to_numpy(counts).reshape(n, 64)
+    for i in range(n):
+        assert np.array_equal(got[i], want[i] * np.uint64(3)), "row %d: start %d, length %d, w=%d" % (
+            i, starts[i], lens[i], widths[i])
+
+
 @pytest.mark.parametrize("tiles_per_item", (0, 1 << 18))
 def test_arrays_beyond_4GiB_in_one_plan(ppc, tiles_per_item, tmp_path, monkeypatch):
     """Maximum sizes in the batched form: a 5 GiB + 13-byte array (over 2^18
