@@ -139,9 +139,11 @@ ppc_status ppc_read_roofline_timed(uint64_t *sink, const void *buf, size_t nbyte
 
 /* ------------------------------------------------------------------------
  * Batched form: thousands of arrays of uneven length and mixed width in one
- * persistent launch.  Same arithmetic as the plain call for every array
- * (the width only selects the final accumulation, Section 5), so each
- * array's counts are exactly what ppc_pospopcnt would add.
+ * persistent launch (a plan runs arrays shorter than one 16 KiB tile in a
+ * second kernel of its own, captured in the same graph).  Same arithmetic
+ * as the plain call for every array (the width only selects the final
+ * accumulation, Section 5), so each array's counts are exactly what
+ * ppc_pospopcnt would add.
  * ---------------------------------------------------------------------- */
 typedef struct ppc_desc {
     const void *buf;   /* device pointer, any alignment                     */
