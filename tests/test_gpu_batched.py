@@ -211,8 +211,10 @@ def test_every_short_length_and_offset_in_one_plan(ppc, w):
     """The short sweep of the plain-call tests -- every length 0..4096 at
     every start offset 0..63, between 0xFF guard bytes -- as ONE batched
     plan of 262,208 arrays, run twice (the replay adds the same counts
-    again).  Covers the batched walk of empty arrays, head/tail-only arrays,
-    short single-chunk arrays and partial tiles on every case."""
+    again).  Covers the plan's small-array kernel on empty arrays,
+    head/tail-only arrays, single-chunk arrays and partial tiles; the
+    batched walk's own short paths are covered by
+    test_walk_short_paths_on_last_items."""
     max_len, n_off, lo, hi = 4096, 64, 64, 128
     region = synth.random_bytes(max_len + n_off, seed=2)
     host = np.concatenate([np.full(lo, 0xFF, np.uint8), region, np.full(hi, 0xFF, np.uint8)])
@@ -240,10 +242,10 @@ def test_every_short_length_and_offset_in_one_plan(ppc, w):
 @pytest.mark.parametrize("w", (8, 16, 32, 64))
 def test_partial_tiles_of_4_to_16_KiB(ppc, w):
     """Arrays of 4,080..16,392 bytes (every 8th length) at start offsets 0, 3,
-    16 and 63: no whole tile, a partial tile of 4..16 chunks per lane (the
-    short partial-tile walk up to 14, the full one above), counted by one
-    plan and, every 17th length, by plain calls; every count equals the
-    oracle's."""
+    16 and 63: at most one tile, 4..16 chunks per lane, counted by one plan
+    (its small-array kernel) and, every 17th length, by plain calls (the
+    walk's short partial-tile path up to 14 chunks per lane, the full one
+    above); every count equals the oracle's."""
     lo, hi, max_len = 64, 128, 16392
     offsets, lengths = (0, 3, 16, 63), list(range(4080, max_len + 1, 8))
     region = synth.random_bytes(max_len + 64, seed=70 + w)
@@ -272,16 +274,52 @@ def test_partial_tiles_of_4_to_16_KiB(ppc, w):
         assert np.array_equal(ppc.counts_to_numpy(one), want[r]), "plain: start %d, length %d" % (starts[r], lens[r])
 
 
-@pytest.mark.parametrize("k_max", (1, 2, 3, 4, 6, 8, 11, 14, 15))
+@pytest.mark.parametrize("w", (8, 16, 32, 64))
+def test_walk_short_paths_on_last_items(ppc, w):
+    """The batched walk's short paths in a plan: arrays of one whole tile
+    plus 0..4,096 bytes (every 8th length) and plus 4,096..16,392 bytes
+    (every 56th), at start offsets 0, 3, 16 and 63, split into items of one
+    tile.  From 32 extra bytes on, at every offset, an array holds more than
+    one tile, so the plan's walk takes it, and its last item holds no whole
+    tile and a partial tile of at most one chunk per lane (the half-adder
+    path), of 2..14 (the carry-save path without the top counter) or of 15
+    and 16 (the full walk); every count equals the oracle's."""
+    lo, hi, tile = 64, 128, 16384
+    extra = list(range(0, 4097, 8)) + list(range(4096 + 56, 16393, 56))
+    offsets = (0, 3, 16, 63)
+    region = synth.random_bytes(tile + max(extra) + 64, seed=80 + w)
+    host = np.concatenate([np.full(lo, 0xFF, np.uint8), region, np.full(hi, 0xFF, np.uint8)])
+    buf = torch.from_numpy(host).to(dev())
+    starts = [lo + o for o in offsets for _ in extra]
+    lens = [tile + e for _ in offsets for e in extra]
+    rows = len(lens)
+    want = oracle.pospopcnt_ranges(host, starts, lens, [w] * rows)
+    counts = torch.zeros((rows, w), dtype=torch.int64, device=dev())
+    base, cbase = buf.data_ptr(), counts.data_ptr()
+    descs = ppc.make_descs([base + s for s in starts], lens, [cbase + r * w * 8 for r in range(rows)], [w] * rows)
+    plan = ppc.ppc_plan_create(descs, rows, ppc.ppc_plan_opts(1, 0, 0, 1, 0))
+    try:
+        ppc.ppc_plan_run(plan)
+        torch.cuda.synchronize()
+        info = ppc.ppc_plan_get_info(plan)
+    finally:
+        ppc.ppc_plan_destroy(plan)
+    assert info["tiles_per_item"] == 1
+    got = ppc.counts_to_numpy(counts).reshape(rows, w)
+    for r in range(rows):
+        assert np.array_equal(got[r], want[r]), "start %d, length %d" % (starts[r], lens[r])
+
+
+@pytest.mark.parametrize("k_max", (1, 2, 3, 4, 6, 8, 11, 14, 15, 16))
 def test_small_array_kernel_chunk_classes(ppc, k_max):
     """Plans give arrays shorter than one tile, of at most 14 chunks per lane,
     to a kernel of their own, built for 1, 2, 4, 8 or 14 chunks per lane by
     the batch's longest such array.  A batch whose longest array holds
-    k_max * 1024 bytes (k_max chunks per lane from an aligned start; at 15 it
-    is no longer small), lengths from 0 up to that at every start residue
-    mod 16, arrays of a tile or more beside them and arrays that share
-    counter rows: after a graph replay, a second replay and a run without the
-    graph every row holds three times the oracle's counts."""
+    k_max * 1024 bytes (k_max chunks per lane from an aligned start; at 15
+    and 16 it is no longer small), lengths from 0 up to that at every start
+    residue mod 16, arrays of more than a tile beside them and arrays that
+    share counter rows: after a graph replay, a second replay and a run
+    without the graph every row holds three times the oracle's counts."""
     rng = np.random.default_rng(900 + k_max)
     top, lo = k_max * 1024, 64
     region = synth.random_bytes(top + 80 * 1024, seed=900 + k_max)
@@ -289,7 +327,7 @@ def test_small_array_kernel_chunk_classes(ppc, k_max):
     buf = torch.from_numpy(host).to(dev())
     assert buf.data_ptr() % 16 == 0
     fixed = [0, 1, 15, 16, 17, 31, 1023, 1024, 1025, top - 1, top, top + 15]
-    lens = fixed + [int(x) for x in rng.integers(0, top + 16, size=240)] + [16384, 20000, 65539]
+    lens = fixed + [int(x) for x in rng.integers(0, top + 16, size=240)] + [16400, 20000, 65539]
     offs = [0] * len(fixed) + [int(x) for x in rng.integers(0, 16, size=240)] + [0, 5, 9]
     offs[len(fixed) - 1] = 7  # top + 15 bytes from an unaligned start as well
     n = len(lens)
