@@ -215,8 +215,8 @@ ppc_status ppc_plan_destroy(ppc_plan *plan);
  * Memory.  Every table the kernels use (array table, block sums, work
  * items, work cursor) lives in one static device array of
  * PPC_NOALLOC_SCRATCH_BYTES (about 8 MiB) per GPU, held until the process
- * ends; the call enqueues two kernels (four for more than 256 arrays) and
- * no copy, and calls no allocating routine.  Calls that
+ * ends; the call enqueues three kernels (five for more than 256 arrays)
+ * and no copy, and calls no allocating routine.  Calls that
  * overlap on one GPU (other streams, other host threads) share that array
  * and race: order them on one stream.  PPC_EDEVICE if a launch fails.
  * ---------------------------------------------------------------------- */

@@ -15,8 +15,10 @@
 // Setup on the device, one thread per array: for at most 256 arrays one
 // kernel, else three (array table and block sums; walk grid, item size and
 // per-block item counts; item offsets and the items themselves), then the
-// persistent kernel that walks the items.  Nothing is allocated and nothing
-// is copied from the host, so the call can be captured.
+// persistent kernel that walks the items, then, for a batch of short
+// arrays, the plan's small-array kernel pattern over the arrays shorter
+// than one tile (they then get no work items; see is_small_array).  Nothing is allocated and nothing is copied
+// from the host, so the call can be captured.
 //
 // Each GPU holds one copy of `scratch` for as long as the process runs;
 // calls that overlap on one GPU (different streams, or several host
@@ -91,7 +93,7 @@ struct NaHeader {
     uint32_t ok;         // 1: every descriptor valid and the items fit the table
     uint32_t n_bad;      // invalid descriptors
     uint32_t waves;      // waves of the walk that take tickets
-    uint32_t reserved0;
+    uint32_t small_apart;  // 1: arrays shorter than one tile get no items; noalloc_small_kernel counts them
     NaSegment seg[kNaSegments];
     uint32_t reserved[52];
 };
@@ -182,7 +184,8 @@ struct NaSlots {
     uint32_t f_rest;
 };
 
-__device__ __forceinline__ NaSlots na_claim(const ArrayInfo &ai, uint32_t P, uint32_t *bucket_cnt) {
+__device__ __forceinline__ NaSlots na_claim(const ArrayInfo &ai, uint32_t P, bool small_apart, uint32_t *bucket_cnt) {
+    if (small_apart && is_small_array(ai)) return NaSlots{0u, 0u, -1, 0u};  // noalloc_small_kernel counts it
     const bool edges = ai.edge0_len + ai.edge1_len > 0u;
     const uint32_t rest = ai.n_tiles % P;
     NaSlots sl{ai.n_tiles / P, 0u, -1, 0u};
@@ -215,9 +218,10 @@ __device__ __forceinline__ ArrayInfo na_array_entry(const ppc_desc *__restrict__
 }
 
 struct NaChoice {
-    uint32_t waves;  // walking waves
-    uint32_t P;      // tiles per whole item
-    bool ok;         // every descriptor valid and the items fit the table
+    uint32_t waves;    // walking waves
+    uint32_t P;        // tiles per whole item
+    bool ok;           // every descriptor valid and the items fit the table
+    bool small_apart;  // short batch: its arrays shorter than one tile go to noalloc_small_kernel
 };
 
 // Walking waves and item size for T tiles over n arrays on `cus` CUs.
@@ -225,12 +229,14 @@ __device__ __forceinline__ NaChoice na_choose(uint64_t T, uint32_t n_bad, uint32
     // every array gives at most n_tiles/P + 1 items, so P >= T / (kNaMaxItems
     // - n) keeps the total within the table
     const uint64_t room = (uint64_t)kNaMaxItems - n;
-    const uint32_t waves = (T < kNaShortMeanTiles * n ? kNaWavesPerCuSmall : kNaWavesPerCu) * max(cus, 1u);
+    const bool short_batch = T < kNaShortMeanTiles * n;
+    const uint32_t waves = (short_batch ? kNaWavesPerCuSmall : kNaWavesPerCu) * max(cus, 1u);
     const uint64_t per_wave = (uint64_t)kNaItemsPerWave * waves;
     const uint64_t bal =
         min(max((T + per_wave - 1) / per_wave, (uint64_t)kNaMinItemTiles), (uint64_t)kNaMaxItemTilesBal);
     const uint64_t p64 = max(bal, (T + room - 1) / room);
-    return NaChoice{waves, (uint32_t)min(p64, (uint64_t)kMaxItemTiles), n_bad == 0u && p64 <= (uint64_t)kMaxItemTiles};
+    return NaChoice{waves, (uint32_t)min(p64, (uint64_t)kMaxItemTiles), n_bad == 0u && p64 <= (uint64_t)kMaxItemTiles,
+                    short_batch};
 }
 
 // Start of each bucket's items in the table (whole items first, then the
@@ -296,6 +302,7 @@ __device__ void na_write_header(NaHeader *h, const uint32_t *tot, const NaChoice
         h->ok = c.ok ? 1u : 0u;
         h->n_bad = n_bad;
         h->waves = c.waves;
+        h->small_apart = c.small_apart ? 1u : 0u;
         if (n_invalid_out) *n_invalid_out = c.ok ? 0u : (n_bad ? n_bad : n);
     }
 }
@@ -324,7 +331,7 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_setup_one_block_kerne
     block_exclusive_scan<uint64_t, 1>(tiles, lds64, T);
     const NaChoice c = na_choose(T[0], n_bad[0], n, cus);
     NaSlots sl{0u, 0u, -1, 0u};
-    if (c.ok && i < n) sl = na_claim(ai, c.P, bucket_cnt);
+    if (c.ok && i < n) sl = na_claim(ai, c.P, c.small_apart, bucket_cnt);
     __syncthreads();
     if (i < (uint32_t)kWave) na_write_header(h, bucket_cnt, c, n_bad[0], n, n_invalid_out, lbase);
     __syncthreads();
@@ -374,7 +381,7 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_count_kernel(uint32_t
     block_exclusive_scan<uint64_t, 1>(tiles, lds64, T);
     const NaChoice c = na_choose(T[0], n_bad[0], n, cus);
     const uint32_t i = blockIdx.x * kNaSetupThreads + tid;
-    if (c.ok && i < n) (void)na_claim(arrays[i], c.P, bucket_cnt);
+    if (c.ok && i < n) (void)na_claim(arrays[i], c.P, c.small_apart, bucket_cnt);
     __syncthreads();
     if (tid <= (uint32_t)kNaBuckets) part[blockIdx.x].cnt[tid] = bucket_cnt[tid];
     if (blockIdx.x == 0 && tid == 0) {
@@ -382,6 +389,7 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_count_kernel(uint32_t
         h->ok = c.ok ? 1u : 0u;
         h->n_bad = n_bad[0];
         h->waves = c.waves;
+        h->small_apart = c.small_apart ? 1u : 0u;
     }
 }
 
@@ -398,7 +406,7 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_items_kernel(uint32_t
     __shared__ uint32_t lds32[kNaBuckets + 1][kNaSetupWaves];
     __shared__ uint32_t bucket_cnt[kNaBuckets + 1], start[kNaBuckets + 1], ltot[kNaBuckets + 1];
     const uint32_t tid = threadIdx.x, nb = gridDim.x;
-    const NaChoice c{h->waves, h->tiles_per_item, h->ok != 0u};
+    const NaChoice c{h->waves, h->tiles_per_item, h->ok != 0u, h->small_apart != 0u};
     const uint32_t n_bad = h->n_bad;
     if (tid <= (uint32_t)kNaBuckets) bucket_cnt[tid] = 0u;
 
@@ -417,7 +425,7 @@ __global__ __launch_bounds__(kNaSetupThreads) void noalloc_items_kernel(uint32_t
     const uint32_t i = blockIdx.x * kNaSetupThreads + tid;
     if (c.ok && i < n) {
         const ArrayInfo ai = arrays[i];
-        const NaSlots sl = na_claim(ai, c.P, bucket_cnt);
+        const NaSlots sl = na_claim(ai, c.P, c.small_apart, bucket_cnt);
         na_write_items(ai, i, c.P, sl, start[kNaBuckets] + sl.f_whole, sl.b >= 0 ? start[sl.b] + sl.f_rest : 0u,
                        items);
     }
@@ -464,6 +472,46 @@ __global__ __launch_bounds__(WPB *kWave) void noalloc_batched_kernel(uint8_t *sc
     }
 }
 
+// The arrays shorter than one tile of a short batch (fewer than
+// kNaShortMeanTiles tiles per array on average), which the walk then has
+// no items for.  In other batches they stay in the walk, where they fill
+// its tail, and this kernel returns at once; so it does if the setup found
+// an invalid descriptor.  Wave g of nw owns array entries g, g + nw,
+// g + 2 nw, ... (at most 64: the host sizes the grid for it), so that the
+// waves work through the table side by side.  Lane l reads entry g + l * nw,
+// a ballot marks the small ones with anything to count, and the wave
+// counts those in order (the next one's entry is loaded while the current
+// array runs).  Built for the largest such array, 14 chunks per lane, at 4
+// waves per SIMD.
+__global__ __launch_bounds__(kSmallWpb *kWave) __attribute__((amdgpu_waves_per_eu(4, 4))) void
+noalloc_small_kernel(const uint8_t *scr, uint32_t n) {
+    const NaHeader *h = reinterpret_cast<const NaHeader *>(scr);
+    const ArrayInfo *arrays = reinterpret_cast<const ArrayInfo *>(scr + kNaArraysOff);
+    const uint32_t nw = gridDim.x * kSmallWpb;
+    const uint32_t g = blockIdx.x * kSmallWpb + wave_in_block();
+    if (g >= n || __builtin_amdgcn_readfirstlane((int)(h->ok & h->small_apart)) == 0) return;
+    const uint64_t mine_idx = (uint64_t)g + (uint64_t)__lane_id() * nw;
+    bool mine = false;
+    if (mine_idx < n) {
+        const ArrayInfo &a = arrays[mine_idx];
+        mine = is_small_array(a) && a.n_chunks + a.edge0_len + a.edge1_len > 0u;
+    }
+    uint64_t m = __ballot(mine);
+    if (m == 0u) return;
+    uint32_t j = (uint32_t)__builtin_ctzll(m);
+    m &= m - 1u;
+    ArrayInfo ai = arrays[g + j * nw];
+    for (;;) {
+        const uint32_t nj = m != 0u ? (uint32_t)__builtin_ctzll(m) : j;
+        const ArrayInfo nai = arrays[g + nj * nw];  // the current entry again after the last
+        run_small_array<kSmallMaxK>(ai);
+        if (m == 0u) break;
+        m &= m - 1u;
+        j = nj;
+        ai = nai;
+    }
+}
+
 // Device address of `scratch` per device, taken once with that device
 // current (each device has its own copy of the array).
 static std::mutex g_na_mu;
@@ -506,9 +554,16 @@ ppc_status ppc_batch_noalloc(const ppc_desc *descs, uint32_t n, uint32_t *n_inva
         hipLaunchKernelGGL(noalloc_count_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, n, cus, scr);
         hipLaunchKernelGGL(noalloc_items_kernel, dim3(nb), dim3(kNaSetupThreads), 0, st, n, n_invalid, scr);
     }
-    if (n > 0)
+    if (n > 0) {
         hipLaunchKernelGGL(noalloc_batched_kernel<kNaWpb>, dim3((waves + kNaWpb - 1) / kNaWpb), dim3(kNaWpb * kWave),
                            0, st, scr);
+        // one round of resident blocks (4 waves per SIMD) unless that leaves
+        // a wave more than 64 array entries, and no wave without one
+        const uint32_t per_wave_max = 64u * kSmallWpb;
+        const uint32_t sb = std::max<uint32_t>(std::min<uint32_t>(4u * cus, (n + kSmallWpb - 1) / kSmallWpb),
+                                               (n + per_wave_max - 1) / per_wave_max);
+        hipLaunchKernelGGL(noalloc_small_kernel, dim3(sb), dim3(kSmallWpb * kWave), 0, st, scr, n);
+    }
     return hipGetLastError() == hipSuccess ? PPC_OK : PPC_EDEVICE;
 }
 
