@@ -131,7 +131,8 @@ __device__ __forceinline__ void run_items(const ArrayInfo *__restrict__ arrays, 
 // walk (63-108 VGPRs against 223), so a kernel built for them alone runs
 // 4 or 8 waves per SIMD instead of 2: two to four times as many of these
 // short, latency-bound items keep their loads in flight.  Plans give such
-// arrays to this kernel.
+// arrays to this kernel; the allocation-free call does in batches of short
+// arrays.
 constexpr uint32_t kSmallMaxK = 14;
 constexpr int kSmallWpb = 4;
 
