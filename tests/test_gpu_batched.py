@@ -274,6 +274,35 @@ def test_partial_tiles_of_4_to_16_KiB(ppc, w):
         assert np.array_equal(ppc.counts_to_numpy(one), want[r]), "plain: start %d, length %d" % (starts[r], lens[r])
 
 
+def test_plan_graph_replays_with_eager_work_between(ppc):
+    """A plan's graph (cursor reset, the persistent kernel, the small-array
+    kernel) replayed five times, with eager work and a plain call between
+    the replays and a synchronisation after each: every replay adds exactly
+    one run's counts (tolerance 0) for the arrays of a tile or more and for
+    those shorter than one tile."""
+    spec = synth.batch_spec(2000, seed=33, lo=16, hi=4 * MiB, start_jitter=64)
+    n = len(spec["lengths"])
+    pool = make_pool(spec, seed=33)
+    counts = torch.zeros((n, 64), dtype=torch.int64, device=dev())
+    want = oracle_rows(pool.cpu().numpy(), spec, range(n))
+    small = sum(1 for L in spec["lengths"] if int(L) < 14 * 1024)
+    assert 200 < small < n - 200  # both kernels have arrays
+    plan = plan_for(ppc, pool, spec, counts, opts(ppc, tiles=16, waves=1024))
+    eager = torch.zeros(16, dtype=torch.int64, device=dev())
+    try:
+        assert ppc.ppc_plan_get_info(plan)["graph"] == 1
+        for r in range(1, 6):
+            ppc.ppc_plan_run(plan)
+            x = torch.randn(512, 512, device=dev())
+            y = (x @ x).abs().sum()
+            ppc.ppc_pospopcnt16(eager, pool[:1 << 20])
+            torch.cuda.synchronize()
+            assert torch.isfinite(y)
+            check_rows(ppc.counts_to_numpy(counts), spec, want, reps=r)
+    finally:
+        ppc.ppc_plan_destroy(plan)
+
+
 @pytest.mark.parametrize("w", (8, 16, 32, 64))
 def test_walk_short_paths_on_last_items(ppc, w):
     """The batched walk's short paths in a plan: arrays of one whole tile

@@ -261,33 +261,42 @@ def test_random_batches_match_the_plan_and_the_oracle(ppc):
 
 def test_captured_in_a_graph_and_replayed(ppc):
     """The call records into a HIP graph (torch.cuda.CUDAGraph capturing on
-    its own stream): every replay adds exactly one batch's counts, with an
-    eager allocation-free call on another batch and other eager work
-    between the replays (the two calls share the scratch array, in stream
-    order).  Every replay is checked (tolerance 0)."""
+    its own stream): two calls in one graph, on a batch of long arrays and
+    on a short batch (whose arrays below one tile go to the small-array
+    kernel); every replay adds exactly one count of each, with an eager
+    allocation-free call on a third batch and other eager work between the
+    replays (the calls share the scratch array, in stream order).  Every
+    replay is checked (tolerance 0)."""
     spec = synth.batch_spec(300, seed=46, lo=16, hi=2 * MiB, start_jitter=64)
     spec2 = synth.batch_spec(50, seed=47, lo=16, hi=64 * 1024, start_jitter=64)
-    pool, pool2 = make_pool(spec, seed=46), make_pool(spec2, seed=47)
+    spec3 = synth.batch_spec(400, seed=48, lo=16, hi=16 * 1024, start_jitter=64)
+    pool, pool2, pool3 = make_pool(spec, seed=46), make_pool(spec2, seed=47), make_pool(spec3, seed=48)
     counts = torch.zeros((300, 64), dtype=torch.int64, device=dev())
     counts2 = torch.zeros((50, 64), dtype=torch.int64, device=dev())
+    counts3 = torch.zeros((400, 64), dtype=torch.int64, device=dev())
     d1 = to_device(ppc, descs_for(ppc, pool, spec, counts))
     d2 = to_device(ppc, descs_for(ppc, pool2, spec2, counts2))
+    d3 = to_device(ppc, descs_for(ppc, pool3, spec3, counts3))
     want = oracle.pospopcnt_ranges(pool.cpu().numpy(), spec["offsets"], spec["lengths"], spec["widths"])
     want2 = oracle.pospopcnt_ranges(pool2.cpu().numpy(), spec2["offsets"], spec2["lengths"], spec2["widths"])
+    want3 = oracle.pospopcnt_ranges(pool3.cpu().numpy(), spec3["offsets"], spec3["lengths"], spec3["widths"])
 
     side = torch.cuda.Stream()  # warm-up off the capture (first launches, scratch address)
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
         ppc.ppc_batch_noalloc(d1, 300)
+        ppc.ppc_batch_noalloc(d3, 400)
     torch.cuda.synchronize()
     counts.zero_()
+    counts3.zero_()
     torch.cuda.synchronize()
 
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
         ppc.ppc_batch_noalloc(d1, 300)
+        ppc.ppc_batch_noalloc(d3, 400)
     torch.cuda.synchronize()
-    assert not counts.any()  # capturing runs nothing
+    assert not counts.any() and not counts3.any()  # capturing runs nothing
 
     for r in range(1, 5):
         g.replay()
@@ -298,9 +307,13 @@ def test_captured_in_a_graph_and_replayed(ppc):
         assert torch.isfinite(y)
         got = ppc.counts_to_numpy(counts).reshape(300, 64)
         got2 = ppc.counts_to_numpy(counts2).reshape(50, 64)
+        got3 = ppc.counts_to_numpy(counts3).reshape(400, 64)
         for i, row in enumerate(want):
             w = int(spec["widths"][i])
             assert np.array_equal(got[i, :w], row * np.uint64(r)), "replay %d, array %d" % (r, i)
+        for i, row in enumerate(want3):
+            w = int(spec3["widths"][i])
+            assert np.array_equal(got3[i, :w], row * np.uint64(r)), "replay %d, short batch array %d" % (r, i)
         for i, row in enumerate(want2):
             w = int(spec2["widths"][i])
             assert np.array_equal(got2[i, :w], row * np.uint64(r)), "eager call %d, array %d" % (r, i)
