@@ -173,10 +173,12 @@ typedef struct ppc_plan ppc_plan;
 /* Builds a plan for `n` arrays described by the HOST array `descs` (the
  * descriptors are copied; the buffers and counters they point to must stay
  * valid while the plan is used).  Validates every descriptor (PPC_EINVAL if
- * any is bad: same rules as the plain call), splits arrays into work items,
- * picks tiles per item and grid size (opts NULL: autotuned for batches of
- * 64 MiB or more, a default setting below; runs replay a graph), uploads
- * the tables and captures the launch.  Autotuning times candidate settings
+ * any is bad: same rules as the plain call), splits arrays into work items
+ * (an array shorter than one 16 KiB tile, of at most 14 16-byte chunks per
+ * lane, goes whole to the small-array kernel instead), picks tiles per item
+ * and grid size (opts NULL: autotuned for batches of 64 MiB or more with an
+ * array of a tile or more, a default setting otherwise; runs replay a
+ * graph), uploads the tables and captures the launches.  Autotuning times candidate settings
  * on `stream` with the counters redirected to scratch memory, so the
  * caller's counters are untouched; the choice is cached in the text file
  * $PPC_TUNE_CACHE (default ~/.cache/ppc_tune.txt) keyed by device and batch
